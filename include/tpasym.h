@@ -1,0 +1,256 @@
+/*
+ * tpasym: T-odd triple-product asymmetry pass on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Parkes et al., "On model-independent searches for direct CP
+ * violation in multi-body decays", Sect. 5, eq. (4)-(6)):
+ *   for every event of a four-body decay M -> A B C D (or its conjugate Mbar)
+ *   compute the triple product C_T = p_A . (p_B x p_C) in the M rest frame
+ *   (Cbar_T for Mbar, same slots holding the C-conjugate particles), split the
+ *   sample into [I] M(C_T>0), [II] M(C_T<0), [III] Mbar(-Cbar_T>0),
+ *   [IV] Mbar(-Cbar_T<0), count them, integrated and in phase-space bins, and
+ *   form the asymmetries.
+ *
+ * C_T is evaluated without a boost as the Lorentz-invariant determinant
+ *   C_T^inv = det[P; p_A; p_B; p_C] = M * C_T            (P = sum of the four momenta)
+ * rows being contravariant (E, px, py, pz).  Every sign and every bin-edge
+ * comparison is CERTIFIED: it equals the decision on the exact real value of
+ * the stored inputs (float32 storage is promoted exactly).  Decisions are taken
+ * by a fast floating-point tier with a rigorous forward error bound, escalated
+ * to float64 and then to exact integer arithmetic only when the bound does not
+ * decide.  Counts are therefore unique and reproducible bit for bit.
+ *
+ * Conventions of every entry point:
+ *   - Device pointers are plain HIP device pointers; the caller owns all
+ *     buffers and keeps them alive until the enqueued work has completed.
+ *   - Work is enqueued asynchronously on ``stream`` (a hipStream_t, NULL = the
+ *     null stream).  Results are valid after the caller synchronises.
+ *   - Counts and statistics ACCUMULATE (+=): zero them once, then chunks,
+ *     batches or shards simply add up.
+ *   - Return value: TP_OK (0) or a negative tp_status.  All argument checks run
+ *     on the host before anything is enqueued; on error nothing is enqueued and
+ *     no output is touched.  tp_strerror() gives a thread-local message.
+ *   - Events whose decision needs the exact tier beyond its range (a single
+ *     event whose nonzero components span more than 2^107 (float64) / 2^136
+ *     (float32) in magnitude) are counted in tp_stats.n_unresolved and in no
+ *     class; callers must treat n_unresolved != 0 as an error.
+ */
+#ifndef TPASYM_H
+#define TPASYM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TPASYM_VERSION 10000 /* 1.0.0 */
+
+typedef enum {
+    TP_OK = 0,
+    TP_EINVAL = -1,        /* bad argument (null pointer, size, slot, edges ...) */
+    TP_EUNSUPPORTED = -2,  /* valid request this build does not support          */
+    TP_EHIP = -3,          /* a HIP runtime call failed                           */
+    TP_ENOMEM = -4,        /* device allocation failed                            */
+    TP_ERANGE = -5,        /* a size exceeds an implementation limit              */
+    TP_EUNCERTAIN = -6     /* reserved: a decision could not be certified         */
+} tp_status;
+
+/* storage type of the 16 component arrays */
+typedef enum { TP_F32 = 0, TP_F64 = 1 } tp_dtype;
+
+/* arithmetic of the first evaluation tier */
+typedef enum {
+    TP_PREC_F64 = 0,         /* float64 evaluation + bound, exact fallback                    */
+    TP_PREC_F32_RECHECK = 1  /* float32 contraction + bound, float64 recheck, exact fallback;
+                                bins in float64.  Requires TP_F32 storage.                    */
+} tp_precision;
+
+/* One sample of events.  Layout: structure of arrays, 16 contiguous arrays of
+ * n elements, p[slot][c] with c = 0..3 for (E, px, py, pz) in MeV (any unit
+ * works: everything is homogeneous), plus int8 flavour tags (0 = M, 1 = Mbar).
+ * Arrays 16-byte aligned and n a multiple of 4 (float32) / 2 (float64) take
+ * the vector-load path; anything else works through scalar loads. */
+typedef struct {
+    int64_t n;
+    int32_t dtype;            /* tp_dtype */
+    int32_t reserved;
+    const void *p[4][4];      /* device */
+    const int8_t *tag;        /* device */
+} tp_events;
+
+/* Channel: slots of the triple product and of the two decay planes.
+ * triple = (A, B, C): C_T = p_A . (p_B x p_C) in the M rest frame; the three
+ * slots must be distinct.  planes = (i, j, k, l), a permutation of 0..3: the
+ * acoplanarity angle Phi is the angle between the (i, j) and (k, l) planes
+ * in the M rest frame (Sect. 5: a triple-product-type, P-odd coordinate). */
+typedef struct {
+    int32_t triple[3];
+    int32_t planes[4];
+} tp_channel;
+
+typedef enum {
+    /* folded acoplanarity |Phi| in [0, pi].  edges: the cosines
+     * c_0 = 1 > c_1 > ... > c_n = -1 of the angle edges; bin j holds
+     * c_{j+1} < cos|Phi| <= c_j (last bin closed).  The sign of sin Phi is the
+     * sign of a triple product, so folding keeps every event's class and the
+     * [0, 2 pi) histogram is recovered from (bin, class).                      */
+    TP_AXIS_ABSPHI = 0,
+    /* invariant mass of the slots in bit mask ``slots`` (sum of their momenta);
+     * edges increasing, e_0 >= 0; bin j holds e_j <= m < e_{j+1}, last bin
+     * closed; outside -> out of range (Sect. 4.2).                            */
+    TP_AXIS_MASS = 1,
+    /* |cos theta| of slot ``slots`` in the M rest frame, measured against the
+     * M flight direction in the lab; edges 0 = e_0 < ... < e_n = 1, bins as
+     * for MASS.                                                                */
+    TP_AXIS_ABSCOS = 2
+} tp_axis_kind;
+
+typedef struct {
+    int32_t kind;             /* tp_axis_kind */
+    int32_t nbins;            /* 1 .. 1024 */
+    int32_t slots;            /* MASS: bit mask (>= 2 bits); ABSCOS: slot; ABSPHI: unused */
+    int32_t reserved;
+    const double *edges;      /* HOST pointer, nbins + 1 values */
+} tp_axis;
+
+/* naxes = 0: global counts only; 1 or 2 axes, combined bin = i0 * nbins1 + i1.
+ * At most one ABSPHI axis.  Total bins <= 1024. */
+typedef struct {
+    int32_t naxes;
+    int32_t reserved;
+    tp_axis axis[2];
+} tp_binning;
+
+/* Per-sample statistics (device, uint64, accumulated). */
+typedef struct {
+    uint64_t n_events;        /* events processed                                   */
+    uint64_t n_zero;          /* C_T = 0 exactly: in no class                       */
+    uint64_t n_invalid;       /* non-finite component, tag not 0/1, or P not a
+                                 future time-like vector (no rest frame)            */
+    uint64_t n_out_of_range;  /* classified events outside the binning (they stay
+                                 in the global row of the counts)                   */
+    uint64_t n_tier2;         /* events that needed the float64 recheck of the sign
+                                 (TP_PREC_F32_RECHECK only)                         */
+    uint64_t n_tier3;         /* events decided by the exact integer tier           */
+    uint64_t n_unresolved;    /* events beyond the exact tier's range: an error     */
+    uint64_t reserved;
+} tp_stats;
+
+/* Class codes written by tp_compute. */
+enum { TP_CLS_I = 0, TP_CLS_II = 1, TP_CLS_III = 2, TP_CLS_IV = 3, TP_CLS_ZERO = 4,
+       TP_CLS_INVALID = 5, TP_CLS_UNRESOLVED = 6 };
+
+/*
+ * tp_compute -- per-event triple product and class (Sect. 5, eq. (4)).
+ *   cls_out: device int8[n] (class codes above) or NULL.
+ *   ct_out:  device double[n] or NULL: C_T^inv = det[P; p_A; p_B; p_C] = M * C_T
+ *            (float64 estimate; its SIGN is exact, 0.0 exactly for class zero).
+ *   stats:   device tp_stats, accumulated (required).
+ * Class totals are not returned here; use tp_bin with naxes = 0.
+ */
+int tp_compute(const tp_events *ev, const tp_channel *ch, int32_t precision,
+               int8_t *cls_out, double *ct_out, tp_stats *stats, void *stream);
+
+/*
+ * tp_bin -- counts per class, integrated and per phase-space bin (eq. (4)-(6)
+ * need only these counts).
+ *   counts: device uint64[(nbins_total + 1) * 4], row-major [row][class]:
+ *           row 0 = every classified event, row 1 + b = bin b; accumulated.
+ *   stats:  device tp_stats, accumulated.
+ */
+int tp_bin(const tp_events *ev, const tp_channel *ch, const tp_binning *bn, int32_t precision,
+           uint64_t *counts, tp_stats *stats, void *stream);
+
+/* One row of asymmetries.  Value/sigma pairs:
+ *   A_T      = (N_I - N_II) / (N_I + N_II)
+ *   Abar_T   = (N_III - N_IV) / (N_III + N_IV)
+ *   a_CP     = (A_T - Abar_T) / 2,  a_P = (A_T + Abar_T) / 2   (T-odd analyses)
+ *   A_plus   = A_CP(C_T > 0) = (N_I - N_III) / (N_I + N_III)   eq. (5)
+ *   A_minus  = A_CP(C_T < 0) = (N_II - N_IV) / (N_II + N_IV)   eq. (5)
+ *   A_even   = (A_plus + A_minus) / 2,  A_odd = (A_plus - A_minus) / 2   eq. (6)
+ * sigma of a two-count asymmetry over n events: sqrt((1 - A^2) / n); of a half
+ * sum or difference of two asymmetries of disjoint samples: half the quadrature
+ * sum.  Each value is the exact ratio of integers rounded once (error <= 1 ulp).
+ * A zero denominator gives NaN for value and sigma and sets its flag bit. */
+typedef struct {
+    double A_T, s_A_T, Abar_T, s_Abar_T, a_CP, s_a_CP, a_P, s_a_P;
+    double A_plus, s_A_plus, A_minus, s_A_minus, A_even, s_A_even, A_odd, s_A_odd;
+    uint64_t N[4];
+    uint32_t flags;   /* bit0 N_I+N_II = 0, bit1 N_III+N_IV = 0, bit2 N_I+N_III = 0,
+                         bit3 N_II+N_IV = 0 */
+    uint32_t reserved;
+} tp_asym_row;
+
+/*
+ * tp_asym -- asymmetries of every row of a counts table (host only).
+ *   counts: HOST uint64[(nrows) * 4] as written by tp_bin; out: HOST tp_asym_row[nrows].
+ */
+int tp_asym(const uint64_t *counts, int64_t nrows, tp_asym_row *out);
+
+/*
+ * tp_scp -- binned S_CP significance and chi^2 (eq. (1)) on the same counts,
+ * host only.  mode 0 (P-even test): X = [I]+[II], Xbar = [III]+[IV];
+ * mode 1 (P-odd test): X = [I]+[IV], Xbar = [II]+[III] (Sect. 5).
+ *   counts: HOST uint64[(nbins + 1) * 4] (row 0 ignored); s_out: HOST double[nbins] or NULL.
+ *   alpha = N_tot(X)/N_tot(Xbar); S^i = (N^i(X) - alpha N^i(Xbar)) / sqrt(N^i(X) + alpha^2 N^i(Xbar))
+ *   (0 for an empty bin); chi2 = sum S^i^2, ndf = nbins - 1, p = chi^2 survival function.
+ */
+int tp_scp(const uint64_t *counts, int64_t nbins, int32_t mode, double *s_out,
+           double *chi2, int64_t *ndf, double *pvalue);
+
+/* One sample of a batch. */
+typedef struct {
+    tp_events ev;
+    tp_channel ch;
+    tp_binning bn;
+    uint64_t *counts;   /* device, as for tp_bin */
+    tp_stats *stats;    /* device */
+} tp_sample;
+
+/* Launch shape of the persistent pass.  Zero fields take defaults. */
+typedef struct {
+    int32_t block;          /* threads per workgroup: 256 or 512                    */
+    int32_t wg_per_cu;      /* persistent workgroups per compute unit: 1..16        */
+    int32_t lds_copies;     /* LDS histogram copies per workgroup: 1 .. waves/WG    */
+    int32_t unroll;         /* vector loads in flight per lane per step: 1 or 2      */
+} tp_tuning;
+
+#define TP_BATCH_GRAPH 1    /* capture the launch in a HIP graph on first use and replay it */
+
+/*
+ * tp_batch -- every sample of ``samples`` in one persistent launch: the
+ * workgroups share the total event range, split into equal contiguous parts;
+ * a workgroup switches descriptor and flushes its LDS histogram when it
+ * crosses from one sample into the next.
+ *   tuning: NULL = the autotuned (or default) shape for this workload class.
+ *   flags: TP_BATCH_GRAPH to capture/replay a graph keyed by the exact sample set.
+ */
+int tp_batch(const tp_sample *samples, int32_t nsamples, int32_t precision,
+             const tp_tuning *tuning, int32_t flags, void *stream);
+
+/*
+ * tp_autotune -- time the candidate launch shapes on this batch (into internal
+ * scratch counters: the samples' counts and stats are NOT touched), store the
+ * best in the in-process cache (and in the JSON file named by TP_TUNE_CACHE if
+ * set) and return it in *best.  Synchronises ``stream``.
+ */
+int tp_autotune(const tp_sample *samples, int32_t nsamples, int32_t precision,
+                void *stream, tp_tuning *best);
+
+/* Average duration (ms) of the main pass kernel over the last ``tp_timing_reset``
+ * window, measured with HIP events recorded on the launch stream around each
+ * launch when timing is enabled (tp_timing_enable(1)).  Returns launches counted. */
+int tp_timing_enable(int32_t on);
+int tp_timing_reset(void);
+int tp_timing_read(double *avg_ms, int64_t *launches);
+
+/* Release per-device internal state (workspaces, plans, graphs). */
+int tp_release(void);
+
+const char *tp_strerror(int status);
+int tp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TPASYM_H */

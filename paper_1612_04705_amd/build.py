@@ -1,0 +1,63 @@
+"""Build libtpasym.so (HIP for gfx950) in-tree with hipcc.
+
+Each source is compiled to an object in parallel (the exact tier is slow to
+compile), then linked into one shared library.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+ROOT = os.path.dirname(HERE)
+OBJ = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libtpasym.so")
+
+SOURCES = ["tp_pass.hip", "tp_exact.hip", "tp_host.cpp"]
+FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+    # every fused multiply-add is written explicitly: the error bounds count roundings
+    "-ffp-contract=off", "-fno-fast-math",
+    # no packed fp32 instructions
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-command-line-argument",
+]
+
+
+def _hipcc():
+    return os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+def _compile(src, extra, verbose):
+    obj = os.path.join(OBJ, src + ".o")
+    cmd = [_hipcc(), *FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
+           os.path.join(CSRC, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}{r.stderr}")
+    return obj, r.stderr
+
+
+def build(verbose: bool = False, extra=()) -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    with ThreadPoolExecutor(len(SOURCES)) as ex:
+        res = list(ex.map(lambda s: _compile(s, list(extra), verbose), SOURCES))
+    for _, err in res:
+        if verbose and err.strip():
+            sys.stderr.write(err)
+    cmd = [_hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *[o for o, _ in res], "-o", LIB + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv,
+                extra=["-Rpass-analysis=kernel-resource-usage"] if "-r" in sys.argv else ()))

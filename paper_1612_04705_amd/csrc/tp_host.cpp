@@ -1,0 +1,966 @@
+// Host runtime of libtpasym: argument validation, launch plans, per-stream
+// workspaces, HIP-graph capture and replay, the autotuner, and the host-only
+// reductions (asymmetries of eq. (5)-(6) and the T-odd quantities; S_CP of eq. (1)).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <list>
+#include <map>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/tpasym.h"
+#include "tp_kernel.h"
+
+namespace tpk {
+hipError_t launch_pass(int dtype, int prec, int mode, const KParams &kp, int grid, int block,
+                       size_t lds, hipStream_t st);
+hipError_t launch_exact(int dtype, int mode, const KParams &kp, int grid, hipStream_t st);
+}  // namespace tpk
+
+using namespace tpk;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define TP_HIP(call)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(TP_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+constexpr uint32_t XCAP = 1u << 20;     // exact-tier list capacity per launch
+constexpr int EXACT_GRID = 16;
+constexpr size_t LDS_LIMIT = 64 * 1024;
+
+uint64_t fnv(const void *p, size_t n, uint64_t h = 1469598103934665603ull)
+{
+    const unsigned char *b = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+struct Workspace {
+    void *buf = nullptr;   // xlist | xcount | xdone
+    uint64_t *xlist = nullptr;
+    uint32_t *xcount = nullptr;
+    uint32_t *xdone = nullptr;
+};
+
+struct Plan {
+    std::vector<KSample> hs;
+    std::vector<double> hedges;
+    int64_t vtotal = 0;
+    int hist_stride = 0;
+    int edge_doubles = 0;
+    int dtype = 0;
+    void *dbuf = nullptr;        // device: samples | edges
+    void *pinned = nullptr;      // host copy source
+    hipEvent_t ready = nullptr;
+    hipStream_t made_on = nullptr;
+    KSample *dsamples = nullptr;
+    double *dedges = nullptr;
+};
+
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    Workspace ws;
+};
+
+struct TimingState {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ring;
+    size_t next = 0, used = 0;
+};
+
+struct Device {
+    int cus = 256;
+    std::map<hipStream_t, Workspace> ws;
+    std::unordered_map<uint64_t, Plan *> plans;
+    std::list<uint64_t> lru;
+    std::unordered_map<uint64_t, GraphEntry> graphs;
+    std::map<std::string, tp_tuning> tuned;
+    uint64_t *scratch_counts = nullptr;   // autotune sink
+    size_t scratch_words = 0;
+};
+
+std::mutex g_mu;
+std::map<int, Device> g_dev;
+TimingState g_timing;
+
+Device &device(int id)
+{
+    auto it = g_dev.find(id);
+    if (it != g_dev.end()) return it->second;
+    Device &d = g_dev[id];
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, id) == hipSuccess && v > 0)
+        d.cus = v;
+    return d;
+}
+
+int get_workspace(Device &d, hipStream_t st, Workspace &out)
+{
+    auto it = d.ws.find(st);
+    if (it != d.ws.end()) {
+        out = it->second;
+        return TP_OK;
+    }
+    Workspace w;
+    const size_t bytes = XCAP * sizeof(uint64_t) + 64;
+    if (hipMalloc(&w.buf, bytes) != hipSuccess) return fail(TP_ENOMEM, "workspace allocation failed");
+    w.xlist = static_cast<uint64_t *>(w.buf);
+    w.xcount = reinterpret_cast<uint32_t *>(static_cast<char *>(w.buf) + XCAP * sizeof(uint64_t));
+    w.xdone = w.xcount + 1;
+    TP_HIP(hipMemsetAsync(w.xcount, 0, 64, st));
+    d.ws[st] = w;
+    out = w;
+    return TP_OK;
+}
+
+int new_workspace(hipStream_t st, Workspace &w)
+{
+    const size_t bytes = XCAP * sizeof(uint64_t) + 64;
+    if (hipMalloc(&w.buf, bytes) != hipSuccess) return fail(TP_ENOMEM, "workspace allocation failed");
+    w.xlist = static_cast<uint64_t *>(w.buf);
+    w.xcount = reinterpret_cast<uint32_t *>(static_cast<char *>(w.buf) + XCAP * sizeof(uint64_t));
+    w.xdone = w.xcount + 1;
+    TP_HIP(hipMemsetAsync(w.xcount, 0, 64, st));
+    TP_HIP(hipStreamSynchronize(st));
+    return TP_OK;
+}
+
+// ------------------------------------------------------------------ validation
+int perm_sign(const int *p, int n)
+{
+    int s = 1;
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j)
+            if (p[i] > p[j]) s = -s;
+    return s;
+}
+
+int check_events(const tp_events *ev, int precision)
+{
+    if (!ev) return fail(TP_EINVAL, "events is NULL");
+    if (ev->n < 0) return fail(TP_EINVAL, "n < 0");
+    if (ev->n >= (int64_t(1) << 40)) return fail(TP_ERANGE, "n >= 2^40 events in one sample");
+    if (ev->dtype != TP_F32 && ev->dtype != TP_F64) return fail(TP_EINVAL, "dtype must be TP_F32 or TP_F64");
+    if (precision != TP_PREC_F64 && precision != TP_PREC_F32_RECHECK)
+        return fail(TP_EINVAL, "unknown precision");
+    if (precision == TP_PREC_F32_RECHECK && ev->dtype != TP_F32)
+        return fail(TP_EUNSUPPORTED, "TP_PREC_F32_RECHECK needs float32 storage");
+    if (ev->n > 0) {
+        for (int s = 0; s < 4; ++s)
+            for (int c = 0; c < 4; ++c)
+                if (!ev->p[s][c]) return fail(TP_EINVAL, "component pointer is NULL");
+        if (!ev->tag) return fail(TP_EINVAL, "tag pointer is NULL");
+    }
+    return TP_OK;
+}
+
+int check_channel(const tp_channel *ch)
+{
+    if (!ch) return fail(TP_EINVAL, "channel is NULL");
+    for (int k = 0; k < 3; ++k)
+        if (ch->triple[k] < 0 || ch->triple[k] > 3) return fail(TP_EINVAL, "triple slot out of 0..3");
+    if (ch->triple[0] == ch->triple[1] || ch->triple[0] == ch->triple[2] || ch->triple[1] == ch->triple[2])
+        return fail(TP_EINVAL, "triple slots must be distinct");
+    int seen = 0;
+    for (int k = 0; k < 4; ++k) {
+        if (ch->planes[k] < 0 || ch->planes[k] > 3) return fail(TP_EINVAL, "plane slot out of 0..3");
+        seen |= 1 << ch->planes[k];
+    }
+    if (seen != 15) return fail(TP_EINVAL, "planes must be a permutation of 0..3");
+    return TP_OK;
+}
+
+int check_binning(const tp_binning *bn)
+{
+    if (!bn) return fail(TP_EINVAL, "binning is NULL");
+    if (bn->naxes < 0 || bn->naxes > 2) return fail(TP_EINVAL, "naxes must be 0, 1 or 2");
+    int64_t tot = 1;
+    int nphi = 0;
+    for (int a = 0; a < bn->naxes; ++a) {
+        const tp_axis &ax = bn->axis[a];
+        if (ax.nbins < 1 || ax.nbins > MAXBINS) return fail(TP_EINVAL, "nbins must be in 1..1024");
+        if (!ax.edges) return fail(TP_EINVAL, "edges pointer is NULL");
+        tot *= ax.nbins;
+        for (int k = 0; k <= ax.nbins; ++k)
+            if (!std::isfinite(ax.edges[k])) return fail(TP_EINVAL, "edges must be finite");
+        if (ax.kind == TP_AXIS_ABSPHI) {
+            ++nphi;
+            if (ax.edges[0] != 1.0 || ax.edges[ax.nbins] != -1.0)
+                return fail(TP_EINVAL, "ABSPHI edges must run from cos 0 = 1 down to cos pi = -1");
+            for (int k = 0; k < ax.nbins; ++k)
+                if (!(ax.edges[k] > ax.edges[k + 1])) return fail(TP_EINVAL, "ABSPHI edges must decrease");
+        } else if (ax.kind == TP_AXIS_MASS) {
+            if (__builtin_popcount((unsigned)ax.slots & 15u) < 2 || (ax.slots & ~15))
+                return fail(TP_EINVAL, "MASS slots must be a bit mask of at least two of slots 0..3");
+            if (!(ax.edges[0] >= 0.0)) return fail(TP_EINVAL, "MASS edges must be >= 0");
+            for (int k = 0; k < ax.nbins; ++k)
+                if (!(ax.edges[k] < ax.edges[k + 1])) return fail(TP_EINVAL, "MASS edges must increase");
+            if (ax.edges[ax.nbins] > 1e150) return fail(TP_EINVAL, "MASS edges too large");
+        } else if (ax.kind == TP_AXIS_ABSCOS) {
+            if (ax.slots < 0 || ax.slots > 3) return fail(TP_EINVAL, "ABSCOS slot out of 0..3");
+            if (ax.edges[0] != 0.0 || ax.edges[ax.nbins] != 1.0)
+                return fail(TP_EINVAL, "ABSCOS edges must run from 0 to 1");
+            for (int k = 0; k < ax.nbins; ++k)
+                if (!(ax.edges[k] < ax.edges[k + 1])) return fail(TP_EINVAL, "ABSCOS edges must increase");
+        } else {
+            return fail(TP_EINVAL, "unknown axis kind");
+        }
+    }
+    if (nphi > 1) return fail(TP_EINVAL, "at most one ABSPHI axis");
+    if (tot > MAXBINS) return fail(TP_ERANGE, "more than 1024 bins in total");
+    return TP_OK;
+}
+
+// e^2 bracketed by two doubles: lo <= e^2 <= hi (exact: the FMA residual tells the side)
+void square_bounds(double e, double &lo, double &hi)
+{
+    const double p = e * e;
+    const double r = std::fma(e, e, -p);
+    if (r > 0) {
+        lo = p;
+        hi = std::nextafter(p, INFINITY);
+    } else if (r < 0) {
+        lo = std::nextafter(p, -INFINITY);
+        hi = p;
+    } else {
+        lo = hi = p;
+    }
+}
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// Fill one KSample (kernel order = channel planes).
+void fill_sample(KSample &k, const tp_events &ev, const tp_channel &ch, const tp_binning *bn,
+                 uint64_t *counts, tp_stats *stats, int8_t *cls_out, double *ct_out,
+                 std::vector<double> &edges)
+{
+    std::memset(&k, 0, sizeof k);
+    int inv[4];
+    for (int t = 0; t < 4; ++t) inv[ch.planes[t]] = t;   // channel slot -> kernel slot
+    bool vec = true;
+    for (int t = 0; t < 4; ++t)
+        for (int c = 0; c < 4; ++c) {
+            k.p[t * 4 + c] = ev.p[ch.planes[t]][c];
+            vec = vec && aligned16(ev.p[ch.planes[t]][c]);
+        }
+    k.tag = ev.tag;
+    vec = vec && ((reinterpret_cast<uintptr_t>(ev.tag) & 3u) == 0);
+    k.vec = vec ? 1 : 0;
+    k.n = ev.n;
+    k.counts = counts;
+    k.stats = reinterpret_cast<uint64_t *>(stats);
+    k.cls_out = cls_out;
+    k.ct_out = ct_out;
+    // sigma: C_T^inv = det[p_D; p_A; p_B; p_C] = sgn(D,A,B,C) det[p0..p3]
+    //        det[kernel rows] = sgn(planes) det[p0..p3]
+    int D = 0 + 1 + 2 + 3 - ch.triple[0] - ch.triple[1] - ch.triple[2];
+    int dabc[4] = { D, ch.triple[0], ch.triple[1], ch.triple[2] };
+    k.sigma = perm_sign(dabc, 4) * perm_sign(ch.planes, 4);
+    k.naxes = bn ? bn->naxes : 0;
+    k.nbtot = 0;
+    if (bn && bn->naxes > 0) {
+        k.nbtot = 1;
+        for (int a = 0; a < bn->naxes; ++a) {
+            const tp_axis &ax = bn->axis[a];
+            k.kind[a] = ax.kind;
+            k.nbins[a] = ax.nbins;
+            k.nbtot *= ax.nbins;
+            k.eoff[a] = (int32_t)edges.size();
+            if (ax.kind == TP_AXIS_MASS) {
+                int m = 0;
+                for (int s = 0; s < 4; ++s)
+                    if (ax.slots & (1 << s)) m |= 1 << inv[s];
+                k.slots[a] = m;
+                std::vector<double> lo(ax.nbins + 1), hi(ax.nbins + 1);
+                for (int e = 0; e <= ax.nbins; ++e) square_bounds(ax.edges[e], lo[e], hi[e]);
+                edges.insert(edges.end(), lo.begin(), lo.end());
+                edges.insert(edges.end(), hi.begin(), hi.end());
+                edges.insert(edges.end(), ax.edges, ax.edges + ax.nbins + 1);
+                k.guess_lo[a] = ax.edges[0];
+                k.guess_inv[a] = ax.nbins / (ax.edges[ax.nbins] - ax.edges[0]);
+            } else {
+                k.slots[a] = ax.kind == TP_AXIS_ABSCOS ? inv[ax.slots] : 0;
+                edges.insert(edges.end(), ax.edges, ax.edges + ax.nbins + 1);
+            }
+        }
+    }
+}
+
+struct Req {
+    const tp_events *ev;
+    const tp_channel *ch;
+    const tp_binning *bn;
+    uint64_t *counts;
+    tp_stats *stats;
+    int8_t *cls_out;
+    double *ct_out;
+};
+
+uint64_t plan_key(const std::vector<Req> &rq, int mode)
+{
+    uint64_t h = fnv(&mode, sizeof mode);
+    for (const Req &r : rq) {
+        h = fnv(r.ev, sizeof(tp_events), h);
+        h = fnv(r.ch, sizeof(tp_channel), h);
+        int na = r.bn ? r.bn->naxes : 0;
+        h = fnv(&na, sizeof na, h);
+        for (int a = 0; a < na; ++a) {
+            const tp_axis &ax = r.bn->axis[a];
+            h = fnv(&ax.kind, sizeof(int32_t) * 3, h);
+            h = fnv(ax.edges, sizeof(double) * (ax.nbins + 1), h);
+        }
+        h = fnv(&r.counts, sizeof(void *), h);
+        h = fnv(&r.stats, sizeof(void *), h);
+        h = fnv(&r.cls_out, sizeof(void *), h);
+        h = fnv(&r.ct_out, sizeof(void *), h);
+    }
+    return h;
+}
+
+int build_plan(Device &d, const std::vector<Req> &rq, int mode, hipStream_t st, Plan *&out)
+{
+    const uint64_t key = plan_key(rq, mode);
+    auto it = d.plans.find(key);
+    if (it != d.plans.end()) {
+        out = it->second;
+        if (out->made_on != st) TP_HIP(hipStreamWaitEvent(st, out->ready, 0));
+        return TP_OK;
+    }
+    Plan *p = new Plan();
+    p->dtype = rq.empty() ? 0 : rq[0].ev->dtype;
+    int64_t v = 0;
+    for (const Req &r : rq) {
+        KSample k;
+        fill_sample(k, *r.ev, *r.ch, mode == 0 ? r.bn : nullptr, r.counts, r.stats, r.cls_out, r.ct_out,
+                    p->hedges);
+        k.vstart = v;
+        v += (r.ev->n + 3) & ~int64_t(3);
+        p->hs.push_back(k);
+        const int stride = (k.nbtot + 1) * 4 + NSTAT;
+        p->hist_stride = std::max(p->hist_stride, stride);
+        int ed = 0;
+        for (int a = 0; a < k.naxes; ++a) ed += edge_doubles(k.kind[a], k.nbins[a]);
+        p->edge_doubles = std::max(p->edge_doubles, ed);
+    }
+    p->vtotal = v;
+    if (p->hedges.empty()) p->hedges.push_back(0.0);
+    const size_t sb = p->hs.size() * sizeof(KSample);
+    const size_t eb = p->hedges.size() * sizeof(double);
+    const size_t tot = ((sb + 255) & ~size_t(255)) + eb;
+    if (hipMalloc(&p->dbuf, tot) != hipSuccess) {
+        delete p;
+        return fail(TP_ENOMEM, "plan table allocation failed");
+    }
+    if (hipHostMalloc(&p->pinned, tot, hipHostMallocDefault) != hipSuccess) {
+        hipFree(p->dbuf);
+        delete p;
+        return fail(TP_ENOMEM, "pinned staging allocation failed");
+    }
+    std::memcpy(p->pinned, p->hs.data(), sb);
+    std::memcpy(static_cast<char *>(p->pinned) + ((sb + 255) & ~size_t(255)), p->hedges.data(), eb);
+    p->dsamples = static_cast<KSample *>(p->dbuf);
+    p->dedges = reinterpret_cast<double *>(static_cast<char *>(p->dbuf) + ((sb + 255) & ~size_t(255)));
+    TP_HIP(hipMemcpyAsync(p->dbuf, p->pinned, tot, hipMemcpyHostToDevice, st));
+    TP_HIP(hipEventCreateWithFlags(&p->ready, hipEventDisableTiming));
+    TP_HIP(hipEventRecord(p->ready, st));
+    p->made_on = st;
+    d.plans[key] = p;
+    d.lru.push_back(key);
+    if (d.lru.size() > 256) {
+        const uint64_t old = d.lru.front();
+        d.lru.pop_front();
+        Plan *q = d.plans[old];
+        // the plan may still be read by enqueued work: wait for it
+        hipEventSynchronize(q->ready);
+        hipDeviceSynchronize();
+        hipFree(q->dbuf);
+        hipHostFree(q->pinned);
+        hipEventDestroy(q->ready);
+        delete q;
+        d.plans.erase(old);
+    }
+    out = p;
+    return TP_OK;
+}
+
+void defaults(Device &d, tp_tuning &t, int64_t vtotal)
+{
+    if (t.block != 256 && t.block != 512) t.block = 256;
+    if (t.wg_per_cu < 1 || t.wg_per_cu > 16) t.wg_per_cu = 4;
+    const int waves = t.block / 64;
+    if (t.lds_copies < 1 || t.lds_copies > waves) t.lds_copies = waves;
+    if (t.unroll < 1 || t.unroll > 2) t.unroll = 1;
+    (void)d;
+    (void)vtotal;
+}
+
+int launch_plan(Device &d, const Plan &p, const tp_tuning &tu_in, int prec, int mode, const Workspace &ws,
+                hipStream_t st)
+{
+    tp_tuning tu = tu_in;
+    defaults(d, tu, p.vtotal);
+    if (p.vtotal == 0) return TP_OK;
+    const int epl = p.dtype == TP_F32 ? 4 : 2;
+    int copies = tu.lds_copies;
+    size_t hist_bytes = 0;
+    for (;;) {
+        hist_bytes = ((size_t)copies * p.hist_stride * 4 + 15) & ~size_t(15);
+        if (hist_bytes + (size_t)p.edge_doubles * 8 <= LDS_LIMIT || copies == 1) break;
+        --copies;
+    }
+    const size_t lds = hist_bytes + (size_t)p.edge_doubles * 8;
+    if (lds > LDS_LIMIT) return fail(TP_ERANGE, "histogram does not fit in LDS");
+    const int64_t tile = (int64_t)epl * tu.block;
+    int64_t grid = (int64_t)d.cus * tu.wg_per_cu;
+    const int64_t need = (p.vtotal + tile - 1) / tile;
+    if (grid > need) grid = need;
+    if (grid < 1) grid = 1;
+    int64_t range = (p.vtotal + grid - 1) / grid;
+    range = (range + tile - 1) / tile * tile;
+    grid = (p.vtotal + range - 1) / range;
+    KParams kp;
+    std::memset(&kp, 0, sizeof kp);
+    kp.samples = p.dsamples;
+    kp.nsamples = (int32_t)p.hs.size();
+    kp.lds_copies = copies;
+    kp.hist_stride = p.hist_stride;
+    kp.edge_doubles = p.edge_doubles;
+    kp.range = range;
+    kp.vtotal = p.vtotal;
+    kp.edges = p.dedges;
+    kp.xlist = ws.xlist;
+    kp.xcount = ws.xcount;
+    kp.xdone = ws.xdone;
+    kp.xcap = XCAP;
+    kp.mode = mode;
+    const bool timed = g_timing.on && !g_timing.ring.empty();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+        auto &pr = g_timing.ring[g_timing.next];
+        e0 = pr.first;
+        e1 = pr.second;
+        TP_HIP(hipEventRecord(e0, st));
+    }
+    TP_HIP(launch_pass(p.dtype, prec, mode, kp, (int)grid, tu.block, lds, st));
+    if (timed) {
+        TP_HIP(hipEventRecord(e1, st));
+        g_timing.next = (g_timing.next + 1) % g_timing.ring.size();
+        g_timing.used = std::min(g_timing.used + 1, g_timing.ring.size());
+    }
+    TP_HIP(launch_exact(p.dtype, mode, kp, EXACT_GRID, st));
+    return TP_OK;
+}
+
+std::string tune_key(const std::vector<Req> &rq, int prec)
+{
+    int64_t n = 0;
+    int maxbins = 0, phi = 0, mass = 0, cosv = 0;
+    for (const Req &r : rq) {
+        n += r.ev->n;
+        if (r.bn) {
+            int tot = 1;
+            for (int a = 0; a < r.bn->naxes; ++a) {
+                tot *= r.bn->axis[a].nbins;
+                phi |= r.bn->axis[a].kind == TP_AXIS_ABSPHI;
+                mass |= r.bn->axis[a].kind == TP_AXIS_MASS;
+                cosv |= r.bn->axis[a].kind == TP_AXIS_ABSCOS;
+            }
+            maxbins = std::max(maxbins, r.bn->naxes ? tot : 0);
+        }
+    }
+    int nb = 0;
+    while ((int64_t(1) << nb) < n) ++nb;
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "d%d_p%d_n2^%d_b%d_ax%d%d%d_s%zu", rq.empty() ? 0 : rq[0].ev->dtype, prec,
+                  nb, maxbins, phi, mass, cosv, rq.size() > 1 ? (size_t)2 : (size_t)1);
+    return buf;
+}
+
+void load_tune_file(Device &d)
+{
+    static bool loaded = false;
+    if (loaded) return;
+    loaded = true;
+    const char *fn = std::getenv("TP_TUNE_CACHE");
+    if (!fn) return;
+    FILE *f = std::fopen(fn, "r");
+    if (!f) return;
+    char key[200];
+    tp_tuning t;
+    while (std::fscanf(f, " \"%199[^\"]\": [%d, %d, %d, %d]%*[,}\n ]", key, &t.block, &t.wg_per_cu,
+                       &t.lds_copies, &t.unroll) == 5)
+        d.tuned[key] = t;
+    std::fclose(f);
+}
+
+void save_tune_file(const Device &d)
+{
+    const char *fn = std::getenv("TP_TUNE_CACHE");
+    if (!fn) return;
+    FILE *f = std::fopen(fn, "w");
+    if (!f) return;
+    std::fprintf(f, "{\n");
+    size_t i = 0;
+    for (auto &kv : d.tuned) {
+        std::fprintf(f, " \"%s\": [%d, %d, %d, %d]%s\n", kv.first.c_str(), kv.second.block, kv.second.wg_per_cu,
+                     kv.second.lds_copies, kv.second.unroll, ++i < d.tuned.size() ? "," : "");
+    }
+    std::fprintf(f, "}\n");
+    std::fclose(f);
+}
+
+int current_device(int &id)
+{
+    TP_HIP(hipGetDevice(&id));
+    return TP_OK;
+}
+
+int run(const std::vector<Req> &rq, int prec, int mode, const tp_tuning *tuning, int flags, hipStream_t st)
+{
+    int dev = 0;
+    int rc = current_device(dev);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Device &d = device(dev);
+    load_tune_file(d);
+    tp_tuning tu;
+    std::memset(&tu, 0, sizeof tu);
+    if (tuning) {
+        tu = *tuning;
+    } else {
+        auto it = d.tuned.find(tune_key(rq, prec));
+        if (it != d.tuned.end()) tu = it->second;
+    }
+    defaults(d, tu, 0);
+    Plan *p = nullptr;
+    rc = build_plan(d, rq, mode, st, p);
+    if (rc) return rc;
+    if (flags & TP_BATCH_GRAPH) {
+        uint64_t gk = plan_key(rq, mode);
+        gk = fnv(&tu, sizeof tu, gk);
+        gk = fnv(&prec, sizeof prec, gk);
+        auto it = d.graphs.find(gk);
+        if (it == d.graphs.end()) {
+            GraphEntry ge;
+            rc = new_workspace(st, ge.ws);
+            if (rc) return rc;
+            hipStream_t cap;
+            TP_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            TP_HIP(hipStreamWaitEvent(cap, p->ready, 0));
+            TP_HIP(hipStreamSynchronize(cap));
+            const bool was_on = g_timing.on;
+            g_timing.on = false;
+            TP_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+            rc = launch_plan(d, *p, tu, prec, mode, ge.ws, cap);
+            hipGraph_t g = nullptr;
+            hipError_t ee = hipStreamEndCapture(cap, &g);
+            g_timing.on = was_on;
+            hipStreamDestroy(cap);
+            if (rc) return rc;
+            if (ee != hipSuccess) return fail(TP_EHIP, std::string("graph capture: ") + hipGetErrorString(ee));
+            ge.graph = g;
+            TP_HIP(hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0));
+            it = d.graphs.emplace(gk, ge).first;
+        }
+        const bool timed = g_timing.on && !g_timing.ring.empty();
+        if (timed) TP_HIP(hipEventRecord(g_timing.ring[g_timing.next].first, st));
+        TP_HIP(hipGraphLaunch(it->second.exec, st));
+        if (timed) {
+            TP_HIP(hipEventRecord(g_timing.ring[g_timing.next].second, st));
+            g_timing.next = (g_timing.next + 1) % g_timing.ring.size();
+            g_timing.used = std::min(g_timing.used + 1, g_timing.ring.size());
+        }
+        return TP_OK;
+    }
+    Workspace ws;
+    rc = get_workspace(d, st, ws);
+    if (rc) return rc;
+    return launch_plan(d, *p, tu, prec, mode, ws, st);
+}
+
+// exact ratio num/den of integers, rounded (long double division, then to double)
+double ratio(__int128 num, __int128 den)
+{
+    return (double)((long double)num / (long double)den);
+}
+
+void two_count(uint64_t a, uint64_t b, double &A, double &sA, bool &empty)
+{
+    const __int128 n = (__int128)a + b;
+    empty = (n == 0);
+    if (empty) {
+        A = sA = NAN;
+        return;
+    }
+    A = ratio((__int128)a - (__int128)b, n);
+    // 1 - A^2 = 4ab / n^2 exactly
+    const double one_m = ratio((__int128)4 * a * b, n * n);
+    sA = std::sqrt(std::max(0.0, one_m) / (double)n);
+}
+
+void half_comb(uint64_t n1, uint64_t n2, uint64_t n3, uint64_t n4, int sgn, double sa, double sb, double &v,
+               double &s)
+{
+    // (A + sgn B)/2 with A = (n1 - n2)/(n1 + n2), B = (n3 - n4)/(n3 + n4)
+    const __int128 N = (__int128)n1 + n2, Nb = (__int128)n3 + n4;
+    if (N == 0 || Nb == 0) {
+        v = s = NAN;
+        return;
+    }
+    const __int128 num = ((__int128)n1 - (__int128)n2) * Nb + sgn * ((__int128)n3 - (__int128)n4) * N;
+    v = ratio(num, 2 * N * Nb);
+    s = 0.5 * std::sqrt(sa * sa + sb * sb);
+}
+
+// Regularised upper incomplete gamma Q(a, x): power series for x < a + 1,
+// Lentz's continued fraction otherwise (Press et al., Numerical Recipes, 6.2).
+double gamma_q(double a, double x)
+{
+    if (x <= 0) return 1.0;
+    const double lg = std::lgamma(a);
+    if (x < a + 1.0) {
+        double ap = a, del = 1.0 / a, sum = del;
+        for (int n = 0; n < 100000; ++n) {
+            ap += 1.0;
+            del *= x / ap;
+            sum += del;
+            if (std::fabs(del) < std::fabs(sum) * 1e-17) break;
+        }
+        return std::max(0.0, 1.0 - sum * std::exp(-x + a * std::log(x) - lg));
+    }
+    const double tiny = 1e-300;
+    double b = x + 1.0 - a, c = 1.0 / tiny, dd = 1.0 / b, h = dd;
+    for (int i = 1; i < 100000; ++i) {
+        const double an = -i * (i - a);
+        b += 2.0;
+        dd = an * dd + b;
+        if (std::fabs(dd) < tiny) dd = tiny;
+        c = b + an / c;
+        if (std::fabs(c) < tiny) c = tiny;
+        dd = 1.0 / dd;
+        const double del = dd * c;
+        h *= del;
+        if (std::fabs(del - 1.0) < 1e-16) break;
+    }
+    return std::exp(-x + a * std::log(x) - lg) * h;
+}
+
+}  // namespace
+
+// ====================================================================== C-ABI
+extern "C" {
+
+int tp_compute(const tp_events *ev, const tp_channel *ch, int32_t precision, int8_t *cls_out, double *ct_out,
+               tp_stats *stats, void *stream)
+{
+    int rc = check_events(ev, precision);
+    if (rc) return rc;
+    rc = check_channel(ch);
+    if (rc) return rc;
+    if (!stats) return fail(TP_EINVAL, "stats is NULL");
+    if (!cls_out && !ct_out) return fail(TP_EINVAL, "tp_compute needs cls_out or ct_out");
+    if (!cls_out) return fail(TP_EINVAL, "cls_out is required (the exact tier writes through it)");
+    if (ev->n == 0) return TP_OK;
+    std::vector<Req> rq{ Req{ ev, ch, nullptr, nullptr, stats, cls_out, ct_out } };
+    return run(rq, precision, 1, nullptr, 0, static_cast<hipStream_t>(stream));
+}
+
+int tp_bin(const tp_events *ev, const tp_channel *ch, const tp_binning *bn, int32_t precision, uint64_t *counts,
+           tp_stats *stats, void *stream)
+{
+    int rc = check_events(ev, precision);
+    if (rc) return rc;
+    rc = check_channel(ch);
+    if (rc) return rc;
+    rc = check_binning(bn);
+    if (rc) return rc;
+    if (!counts || !stats) return fail(TP_EINVAL, "counts and stats are required");
+    if (ev->n == 0) return TP_OK;
+    std::vector<Req> rq{ Req{ ev, ch, bn, counts, stats, nullptr, nullptr } };
+    return run(rq, precision, 0, nullptr, 0, static_cast<hipStream_t>(stream));
+}
+
+int tp_batch(const tp_sample *samples, int32_t nsamples, int32_t precision, const tp_tuning *tuning,
+             int32_t flags, void *stream)
+{
+    if (nsamples < 0 || (nsamples > 0 && !samples)) return fail(TP_EINVAL, "bad sample list");
+    if (nsamples > (1 << 20)) return fail(TP_ERANGE, "too many samples");
+    if (flags & ~TP_BATCH_GRAPH) return fail(TP_EINVAL, "unknown flags");
+    std::vector<Req> rq;
+    int dtype = -1;
+    for (int i = 0; i < nsamples; ++i) {
+        const tp_sample &s = samples[i];
+        int rc = check_events(&s.ev, precision);
+        if (rc) return rc;
+        rc = check_channel(&s.ch);
+        if (rc) return rc;
+        rc = check_binning(&s.bn);
+        if (rc) return rc;
+        if (!s.counts || !s.stats) return fail(TP_EINVAL, "counts and stats are required");
+        if (dtype >= 0 && s.ev.dtype != dtype) return fail(TP_EUNSUPPORTED, "all samples of a batch share one dtype");
+        dtype = s.ev.dtype;
+        rq.push_back(Req{ &s.ev, &s.ch, &s.bn, s.counts, s.stats, nullptr, nullptr });
+    }
+    if (rq.empty()) return TP_OK;
+    return run(rq, precision, 0, tuning, flags, static_cast<hipStream_t>(stream));
+}
+
+int tp_autotune(const tp_sample *samples, int32_t nsamples, int32_t precision, void *stream, tp_tuning *best)
+{
+    if (!best) return fail(TP_EINVAL, "best is NULL");
+    if (nsamples <= 0 || !samples) return fail(TP_EINVAL, "bad sample list");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // validate and size a scratch sink
+    size_t words = 0;
+    for (int i = 0; i < nsamples; ++i) {
+        int rc = check_events(&samples[i].ev, precision);
+        if (rc) return rc;
+        rc = check_channel(&samples[i].ch);
+        if (rc) return rc;
+        rc = check_binning(&samples[i].bn);
+        if (rc) return rc;
+        int tot = 1;
+        for (int a = 0; a < samples[i].bn.naxes; ++a) tot *= samples[i].bn.axis[a].nbins;
+        words += (size_t)(tot + 1) * 4 + NSTAT;
+    }
+    int dev = 0;
+    int rc = current_device(dev);
+    if (rc) return rc;
+    std::vector<Req> rq;
+    std::vector<tp_sample> sink(samples, samples + nsamples);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        Device &d = device(dev);
+        if (d.scratch_words < words) {
+            if (d.scratch_counts) hipFree(d.scratch_counts);
+            if (hipMalloc(&d.scratch_counts, words * 8) != hipSuccess) {
+                d.scratch_counts = nullptr;
+                d.scratch_words = 0;
+                return fail(TP_ENOMEM, "autotune scratch allocation failed");
+            }
+            d.scratch_words = words;
+        }
+        size_t off = 0;
+        for (int i = 0; i < nsamples; ++i) {
+            int tot = 1;
+            for (int a = 0; a < samples[i].bn.naxes; ++a) tot *= samples[i].bn.axis[a].nbins;
+            sink[i].counts = d.scratch_counts + off;
+            off += (size_t)(tot + 1) * 4;
+            sink[i].stats = reinterpret_cast<tp_stats *>(d.scratch_counts + off);
+            off += NSTAT;
+        }
+    }
+    for (auto &s : sink) rq.push_back(Req{ &s.ev, &s.ch, &s.bn, s.counts, s.stats, nullptr, nullptr });
+    std::vector<tp_tuning> cand;
+    for (int wpc : { 1, 2, 4, 8 })
+        for (int copies : { 1, 2, 4 }) {
+            tp_tuning t;
+            t.block = 256;
+            t.wg_per_cu = wpc;
+            t.lds_copies = copies;
+            t.unroll = 1;
+            cand.push_back(t);
+        }
+    hipEvent_t a, b;
+    TP_HIP(hipEventCreate(&a));
+    TP_HIP(hipEventCreate(&b));
+    float best_ms = 1e30f;
+    tp_tuning bt = cand[0];
+    const bool was_on = g_timing.on;
+    g_timing.on = false;
+    for (const tp_tuning &t : cand) {
+        rc = run(rq, precision, 0, &t, 0, st);   // warm-up (and plan build)
+        if (rc) break;
+        TP_HIP(hipEventRecord(a, st));
+        for (int r = 0; r < 3; ++r) {
+            rc = run(rq, precision, 0, &t, 0, st);
+            if (rc) break;
+        }
+        TP_HIP(hipEventRecord(b, st));
+        TP_HIP(hipEventSynchronize(b));
+        float ms = 0;
+        TP_HIP(hipEventElapsedTime(&ms, a, b));
+        if (ms < best_ms) {
+            best_ms = ms;
+            bt = t;
+        }
+    }
+    g_timing.on = was_on;
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    if (rc) return rc;
+    *best = bt;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        Device &d = device(dev);
+        d.tuned[tune_key(rq, precision)] = bt;
+        save_tune_file(d);
+    }
+    return TP_OK;
+}
+
+int tp_asym(const uint64_t *counts, int64_t nrows, tp_asym_row *out)
+{
+    if (!counts || !out) return fail(TP_EINVAL, "null pointer");
+    if (nrows < 0) return fail(TP_EINVAL, "nrows < 0");
+    for (int64_t r = 0; r < nrows; ++r) {
+        const uint64_t *n = counts + r * 4;
+        tp_asym_row &o = out[r];
+        std::memset(&o, 0, sizeof o);
+        for (int k = 0; k < 4; ++k) o.N[k] = n[k];
+        bool e0, e1, e2, e3;
+        two_count(n[0], n[1], o.A_T, o.s_A_T, e0);
+        two_count(n[2], n[3], o.Abar_T, o.s_Abar_T, e1);
+        two_count(n[0], n[2], o.A_plus, o.s_A_plus, e2);
+        two_count(n[1], n[3], o.A_minus, o.s_A_minus, e3);
+        o.flags = (e0 ? 1u : 0u) | (e1 ? 2u : 0u) | (e2 ? 4u : 0u) | (e3 ? 8u : 0u);
+        half_comb(n[0], n[1], n[2], n[3], -1, o.s_A_T, o.s_Abar_T, o.a_CP, o.s_a_CP);
+        half_comb(n[0], n[1], n[2], n[3], +1, o.s_A_T, o.s_Abar_T, o.a_P, o.s_a_P);
+        half_comb(n[0], n[2], n[1], n[3], +1, o.s_A_plus, o.s_A_minus, o.A_even, o.s_A_even);
+        half_comb(n[0], n[2], n[1], n[3], -1, o.s_A_plus, o.s_A_minus, o.A_odd, o.s_A_odd);
+    }
+    return TP_OK;
+}
+
+int tp_scp(const uint64_t *counts, int64_t nbins, int32_t mode, double *s_out, double *chi2, int64_t *ndf,
+           double *pvalue)
+{
+    if (!counts || !chi2 || !ndf || !pvalue) return fail(TP_EINVAL, "null pointer");
+    if (nbins < 1) return fail(TP_EINVAL, "nbins < 1");
+    if (mode != 0 && mode != 1) return fail(TP_EINVAL, "mode must be 0 (P-even) or 1 (P-odd)");
+    std::vector<uint64_t> x(nbins), xb(nbins);
+    __int128 tx = 0, txb = 0;
+    for (int64_t i = 0; i < nbins; ++i) {
+        const uint64_t *n = counts + (i + 1) * 4;
+        x[i] = mode == 0 ? n[0] + n[1] : n[0] + n[3];
+        xb[i] = mode == 0 ? n[2] + n[3] : n[1] + n[2];
+        tx += x[i];
+        txb += xb[i];
+    }
+    double c2 = 0.0;
+    for (int64_t i = 0; i < nbins; ++i) {
+        double s = 0.0;
+        if (txb != 0) {
+            // S = (x - a xb)/sqrt(x + a^2 xb), a = tx/txb:  numerator (x txb - tx xb)/txb,
+            // radicand (x txb^2 + tx^2 xb)/txb^2
+            const __int128 num = (__int128)x[i] * txb - tx * (__int128)xb[i];
+            const long double rad = (long double)x[i] * (long double)txb * (long double)txb +
+                                    (long double)tx * (long double)tx * (long double)xb[i];
+            if (rad > 0) s = (double)((long double)num / sqrtl(rad));
+        }
+        if (s_out) s_out[i] = s;
+        c2 += s * s;
+    }
+    *chi2 = c2;
+    *ndf = nbins - 1;
+    *pvalue = nbins > 1 ? gamma_q(0.5 * (double)(nbins - 1), 0.5 * c2) : NAN;
+    return TP_OK;
+}
+
+int tp_timing_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (on && g_timing.ring.empty()) {
+        g_timing.ring.resize(4096);
+        for (auto &pr : g_timing.ring) {
+            TP_HIP(hipEventCreate(&pr.first));
+            TP_HIP(hipEventCreate(&pr.second));
+        }
+    }
+    g_timing.on = on != 0;
+    g_timing.next = 0;
+    g_timing.used = 0;
+    return TP_OK;
+}
+
+int tp_timing_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_timing.next = 0;
+    g_timing.used = 0;
+    return TP_OK;
+}
+
+int tp_timing_read(double *avg_ms, int64_t *launches)
+{
+    if (!avg_ms || !launches) return fail(TP_EINVAL, "null pointer");
+    std::lock_guard<std::mutex> lk(g_mu);
+    double tot = 0.0;
+    const size_t n = g_timing.used;
+    for (size_t i = 0; i < n; ++i) {
+        auto &pr = g_timing.ring[i];
+        TP_HIP(hipEventSynchronize(pr.second));
+        float ms = 0.0f;
+        TP_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+        tot += ms;
+    }
+    *launches = (int64_t)n;
+    *avg_ms = n ? tot / (double)n : 0.0;
+    return TP_OK;
+}
+
+int tp_release(void)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipDeviceSynchronize();
+    for (auto &kv : g_dev) {
+        Device &d = kv.second;
+        for (auto &w : d.ws) hipFree(w.second.buf);
+        for (auto &p : d.plans) {
+            hipFree(p.second->dbuf);
+            hipHostFree(p.second->pinned);
+            hipEventDestroy(p.second->ready);
+            delete p.second;
+        }
+        for (auto &g : d.graphs) {
+            hipGraphExecDestroy(g.second.exec);
+            hipGraphDestroy(g.second.graph);
+            hipFree(g.second.ws.buf);
+        }
+        if (d.scratch_counts) hipFree(d.scratch_counts);
+    }
+    g_dev.clear();
+    return TP_OK;
+}
+
+const char *tp_strerror(int status)
+{
+    if (!g_err.empty() && status != TP_OK) return g_err.c_str();
+    switch (status) {
+    case TP_OK: return "ok";
+    case TP_EINVAL: return "invalid argument";
+    case TP_EUNSUPPORTED: return "unsupported";
+    case TP_EHIP: return "HIP runtime error";
+    case TP_ENOMEM: return "out of device memory";
+    case TP_ERANGE: return "size beyond an implementation limit";
+    case TP_EUNCERTAIN: return "a decision could not be certified";
+    default: return "unknown status";
+    }
+}
+
+int tp_version(void) { return TPASYM_VERSION; }
+
+}  // extern "C"

@@ -1,0 +1,291 @@
+"""Python binding of libtpasym (include/tpasym.h): argument marshalling only.
+
+Every step of the pass runs in the HIP library.  PyTorch provides device
+memory and the current stream.  If the library is missing this module raises;
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtpasym.so")
+
+TP_F32, TP_F64 = 0, 1
+TP_PREC_F64, TP_PREC_F32_RECHECK = 0, 1
+TP_AXIS_ABSPHI, TP_AXIS_MASS, TP_AXIS_ABSCOS = 0, 1, 2
+TP_BATCH_GRAPH = 1
+CLS_NAMES = ("I", "II", "III", "IV", "zero", "invalid", "unresolved")
+STAT_NAMES = ("n_events", "n_zero", "n_invalid", "n_out_of_range", "n_tier2", "n_tier3", "n_unresolved")
+
+
+class TPError(RuntimeError):
+    pass
+
+
+class _Events(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("p", ctypes.c_void_p * 16), ("tag", ctypes.c_void_p)]
+
+
+class _Channel(ctypes.Structure):
+    _fields_ = [("triple", ctypes.c_int32 * 3), ("planes", ctypes.c_int32 * 4)]
+
+
+class _Axis(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("nbins", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("edges", ctypes.POINTER(ctypes.c_double))]
+
+
+class _Binning(ctypes.Structure):
+    _fields_ = [("naxes", ctypes.c_int32), ("reserved", ctypes.c_int32), ("axis", _Axis * 2)]
+
+
+class _Sample(ctypes.Structure):
+    _fields_ = [("ev", _Events), ("ch", _Channel), ("bn", _Binning),
+                ("counts", ctypes.c_void_p), ("stats", ctypes.c_void_p)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+                ("lds_copies", ctypes.c_int32), ("unroll", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class _AsymRow(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in (
+        "A_T", "s_A_T", "Abar_T", "s_Abar_T", "a_CP", "s_a_CP", "a_P", "s_a_P",
+        "A_plus", "s_A_plus", "A_minus", "s_A_minus", "A_even", "s_A_even", "A_odd", "s_A_odd")] + \
+        [("N", ctypes.c_uint64 * 4), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+ASYM_KEYS = ("A_T", "Abar_T", "a_CP", "a_P", "A_plus", "A_minus", "A_even", "A_odd")
+
+_lib = None
+
+
+def load():
+    """Load libtpasym.so (built by paper_1612_04705_amd.build); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise TPError(f"{LIB_PATH} is missing: build it with `python -m paper_1612_04705_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    sig = {
+        "tp_compute": [P(_Events), P(_Channel), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                       ctypes.c_void_p, ctypes.c_void_p],
+        "tp_bin": [P(_Events), P(_Channel), P(_Binning), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                   ctypes.c_void_p],
+        "tp_asym": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p],
+        "tp_scp": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, P(ctypes.c_double),
+                   P(ctypes.c_int64), P(ctypes.c_double)],
+        "tp_batch": [P(_Sample), ctypes.c_int32, ctypes.c_int32, P(Tuning), ctypes.c_int32, ctypes.c_void_p],
+        "tp_autotune": [P(_Sample), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, P(Tuning)],
+        "tp_timing_enable": [ctypes.c_int32],
+        "tp_timing_reset": [],
+        "tp_timing_read": [P(ctypes.c_double), P(ctypes.c_int64)],
+        "tp_release": [],
+        "tp_strerror": [ctypes.c_int],
+        "tp_version": [],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_char_p if name == "tp_strerror" else ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return ("tp_compute", "tp_bin", "tp_asym", "tp_scp", "tp_batch", "tp_autotune", "tp_timing_enable",
+            "tp_timing_reset", "tp_timing_read", "tp_release", "tp_strerror", "tp_version")
+
+
+def _check(rc):
+    if rc != 0:
+        raise TPError(f"libtpasym error {rc}: {load().tp_strerror(rc).decode()}")
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+# ------------------------------------------------------------------ descriptors
+@dataclass
+class DeviceSample:
+    """16 component tensors (slot-major [s][c]) and the int8 tag tensor on one device."""
+    comps: list
+    tag: torch.Tensor
+
+    @property
+    def n(self):
+        return int(self.tag.numel())
+
+    @staticmethod
+    def from_sample(sample, device="cuda"):
+        comps = [sample.comps[s][c].to(device).contiguous() for s in range(4) for c in range(4)]
+        return DeviceSample(comps, sample.tag.to(device).contiguous())
+
+    def events(self) -> _Events:
+        e = _Events()
+        e.n = self.n
+        dt = self.comps[0].dtype
+        if dt not in (torch.float32, torch.float64) or any(t.dtype != dt for t in self.comps):
+            raise TPError("components must all be float32 or all float64")
+        e.dtype = TP_F32 if dt == torch.float32 else TP_F64
+        for k, t in enumerate(self.comps):
+            if not t.is_contiguous() or t.numel() != self.n:
+                raise TPError("component tensors must be contiguous with n elements")
+            e.p[k] = t.data_ptr()
+        if self.tag.dtype != torch.int8:
+            raise TPError("tag must be int8")
+        e.tag = self.tag.data_ptr()
+        return e
+
+
+def channel(triple, planes=(0, 1, 2, 3)) -> _Channel:
+    c = _Channel()
+    for k in range(3):
+        c.triple[k] = int(triple[k])
+    for k in range(4):
+        c.planes[k] = int(planes[k])
+    return c
+
+
+class Binning:
+    """Holds the edge arrays alive for the lifetime of the descriptor."""
+
+    def __init__(self, axes=()):
+        self._edges = []
+        self.b = _Binning()
+        self.b.naxes = len(axes)
+        self.nbins = []
+        for a, ax in enumerate(axes):
+            e = np.ascontiguousarray(np.asarray(ax.edges, dtype=np.float64))
+            self._edges.append(e)
+            self.b.axis[a].kind = int(ax.kind)
+            self.b.axis[a].nbins = len(e) - 1
+            self.b.axis[a].slots = int(ax.slots)
+            self.b.axis[a].edges = e.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            self.nbins.append(len(e) - 1)
+
+    @property
+    def nrows(self):
+        return int(np.prod(self.nbins)) + 1 if self.nbins else 1
+
+
+def new_counts(binning: Binning, device="cuda"):
+    """Zeroed device counters: counts int64[(nbins+1)*4] (read as uint64) and stats int64[8]."""
+    return (torch.zeros(binning.nrows * 4, dtype=torch.int64, device=device),
+            torch.zeros(8, dtype=torch.int64, device=device))
+
+
+# ------------------------------------------------------------------ entry points
+def compute(ds: DeviceSample, ch: _Channel, precision=TP_PREC_F64, want_ct=True, stats=None, stream=None):
+    """tp_compute: per-event class (int8) and C_T^inv (float64) on the device."""
+    lib = load()
+    ev = ds.events()
+    cls = torch.empty(ds.n, dtype=torch.int8, device=ds.tag.device)
+    ct = torch.empty(ds.n, dtype=torch.float64, device=ds.tag.device) if want_ct else None
+    if stats is None:
+        stats = torch.zeros(8, dtype=torch.int64, device=ds.tag.device)
+    _check(lib.tp_compute(ctypes.byref(ev), ctypes.byref(ch), int(precision), ctypes.c_void_p(cls.data_ptr()),
+                          ctypes.c_void_p(ct.data_ptr()) if ct is not None else None,
+                          ctypes.c_void_p(stats.data_ptr()), _stream(stream)))
+    return cls, ct, stats
+
+
+def bin(ds: DeviceSample, ch: _Channel, bn: Binning, precision=TP_PREC_F64, counts=None, stats=None,
+        stream=None):
+    """tp_bin: accumulate counts [(nbins+1)*4] and stats [8] (device int64 tensors, read as uint64)."""
+    lib = load()
+    ev = ds.events()
+    if counts is None or stats is None:
+        counts, stats = new_counts(bn, ds.tag.device)
+    _check(lib.tp_bin(ctypes.byref(ev), ctypes.byref(ch), ctypes.byref(bn.b), int(precision),
+                      ctypes.c_void_p(counts.data_ptr()), ctypes.c_void_p(stats.data_ptr()), _stream(stream)))
+    return counts, stats
+
+
+class Batch:
+    """A fixed set of samples for tp_batch (keeps every descriptor alive)."""
+
+    def __init__(self, items):
+        """items: list of (DeviceSample, channel, Binning, counts, stats)."""
+        self.items = list(items)
+        self.arr = (_Sample * len(self.items))()
+        for i, (ds, ch, bn, counts, stats) in enumerate(self.items):
+            self.arr[i].ev = ds.events()
+            self.arr[i].ch = ch
+            self.arr[i].bn = bn.b
+            self.arr[i].counts = counts.data_ptr()
+            self.arr[i].stats = stats.data_ptr()
+
+    def run(self, precision=TP_PREC_F32_RECHECK, tuning: Tuning | None = None, graph=False, stream=None):
+        _check(load().tp_batch(self.arr, len(self.items), int(precision),
+                               ctypes.byref(tuning) if tuning is not None else None,
+                               TP_BATCH_GRAPH if graph else 0, _stream(stream)))
+
+    def autotune(self, precision=TP_PREC_F32_RECHECK, stream=None) -> Tuning:
+        t = Tuning()
+        _check(load().tp_autotune(self.arr, len(self.items), int(precision), _stream(stream), ctypes.byref(t)))
+        return t
+
+
+def asym(counts) -> list:
+    """tp_asym on host counts (any integer array of (nrows*4)); list of dicts per row."""
+    c = np.ascontiguousarray(np.asarray(counts, dtype=np.int64).astype(np.uint64))
+    nrows = c.size // 4
+    out = (_AsymRow * nrows)()
+    _check(load().tp_asym(c.ctypes.data_as(ctypes.c_void_p), nrows, ctypes.cast(out, ctypes.c_void_p)))
+    rows = []
+    for r in out:
+        d = {k: (r.__getattribute__(k), r.__getattribute__("s_" + k)) for k in ASYM_KEYS}
+        d["N"] = tuple(int(x) for x in r.N)
+        d["flags"] = int(r.flags)
+        rows.append(d)
+    return rows
+
+
+def scp(counts, mode=1):
+    """tp_scp: (S per bin, chi2, ndf, p-value); mode 0 = P-even test, 1 = P-odd test."""
+    c = np.ascontiguousarray(np.asarray(counts, dtype=np.int64).astype(np.uint64))
+    nbins = c.size // 4 - 1
+    s = np.zeros(max(nbins, 1), dtype=np.float64)
+    chi2, ndf, p = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    _check(load().tp_scp(c.ctypes.data_as(ctypes.c_void_p), nbins, int(mode), s.ctypes.data_as(ctypes.c_void_p),
+                         ctypes.byref(chi2), ctypes.byref(ndf), ctypes.byref(p)))
+    return s[:nbins], chi2.value, ndf.value, p.value
+
+
+def timing_enable(on=True):
+    _check(load().tp_timing_enable(1 if on else 0))
+
+
+def timing_reset():
+    _check(load().tp_timing_reset())
+
+
+def timing_read():
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(load().tp_timing_read(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def release():
+    _check(load().tp_release())
+
+
+def version():
+    return int(load().tp_version())

@@ -1,0 +1,148 @@
+"""libtpasym loads, exports every entry point of include/tpasym.h, and its
+host-only parts (validation, asymmetries, S_CP) behave.  CPU only: no call here
+reaches the GPU (argument checks run before anything is enqueued)."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import exact
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def tp():
+    from paper_1612_04705_amd import tpasym
+    if not os.path.exists(tpasym.LIB_PATH):
+        from paper_1612_04705_amd import build
+        build.build()
+    tpasym.load()
+    return tpasym
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "tpasym.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tp_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(tp):
+    lib = tp.load()
+    names = header_functions()
+    assert "tp_batch" in names and "tp_bin" in names and "tp_compute" in names and "tp_asym" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(tp.exported_symbols())
+    assert tp.version() == 10000
+
+
+def test_asym_matches_exact_fractions(tp):
+    rng = np.random.default_rng(5)
+    rows = [[60, 40, 45, 55], [7, 0, 0, 0], [0, 0, 0, 0], [1, 1, 1, 1], [0, 3, 5, 0]]
+    rows += rng.integers(0, 10 ** 9, size=(200, 4)).tolist()
+    rows += rng.integers(0, 50, size=(50, 4)).tolist()
+    rows += [[2 ** 40 + 3, 2 ** 40 - 7, 2 ** 39, 3 * 2 ** 38 + 1]]
+    got = tp.asym(np.array(rows).ravel())
+    for r, g in zip(rows, got):
+        want = exact.asym_row(r)
+        assert g["N"] == tuple(r)
+        for k in tp.ASYM_KEYS:
+            wv, ws = want[k]
+            gv, gs = g[k]
+            if wv is None:
+                assert math.isnan(gv) and math.isnan(gs)
+                continue
+            assert abs(gv - float(wv)) <= 1e-15 * abs(float(wv)) + 1e-300, (r, k, gv, float(wv))
+            assert abs(gs - ws) <= 1e-12 * ws + 1e-300, (r, k, gs, ws)
+    assert got[2]["flags"] == 15 and got[1]["flags"] == 2 | 8
+
+
+def test_scp_matches_oracle(tp):
+    rng = np.random.default_rng(6)
+    for mode in (0, 1):
+        for nb in (1, 2, 5, 40, 1024):
+            c = rng.integers(0, 5000, size=(nb + 1, 4))
+            c[0] = c[1:].sum(axis=0)
+            s, chi2, ndf, p = tp.scp(c.ravel(), mode)
+            if mode == 0:
+                x, xb = c[1:, 0] + c[1:, 1], c[1:, 2] + c[1:, 3]
+            else:
+                x, xb = c[1:, 0] + c[1:, 3], c[1:, 1] + c[1:, 2]
+            ws, wchi2, wndf, wp = exact.scp([int(v) for v in x], [int(v) for v in xb])
+            assert ndf == wndf
+            np.testing.assert_allclose(s, ws, rtol=1e-13, atol=1e-15)
+            assert chi2 == pytest.approx(wchi2, rel=1e-12)
+            if nb > 1:
+                assert p == pytest.approx(wp, rel=1e-9, abs=1e-300)
+
+
+def _events(tp, n=16, dtype=0, ptr=0x100000):
+    e = tp._Events()
+    e.n = n
+    e.dtype = dtype
+    for k in range(16):
+        e.p[k] = ptr + 64 * k
+    e.tag = ptr + 4096
+    return e
+
+
+def _bn(tp, axes):
+    return tp.Binning(axes)
+
+
+def test_validation_errors_reach_no_device(tp):
+    from paper_1612_04705_amd import synth
+    lib = tp.load()
+    ch = tp.channel((0, 1, 2), (0, 1, 2, 3))
+    good = _bn(tp, [synth.absphi_axis(10)])
+    cnt = ctypes.c_void_p(0x200000)
+    st = ctypes.c_void_p(0x300000)
+
+    def rc_bin(ev, chx, bnx, prec=0, counts=cnt, stats=st):
+        return lib.tp_bin(ctypes.byref(ev) if ev is not None else None,
+                          ctypes.byref(chx) if chx is not None else None,
+                          ctypes.byref(bnx.b) if bnx is not None else None, prec, counts, stats, None)
+
+    assert rc_bin(None, ch, good) == -1
+    assert rc_bin(_events(tp), None, good) == -1
+    assert rc_bin(_events(tp), ch, None) == -1
+    assert rc_bin(_events(tp, n=-1), ch, good) == -1
+    assert rc_bin(_events(tp, dtype=7), ch, good) == -1
+    assert rc_bin(_events(tp, dtype=1), ch, good, prec=1) == -2      # F32 recheck needs float32
+    assert rc_bin(_events(tp), ch, good, prec=5) == -1
+    assert rc_bin(_events(tp), tp.channel((0, 0, 2)), good) == -1
+    assert rc_bin(_events(tp), tp.channel((0, 1, 4)), good) == -1
+    assert rc_bin(_events(tp), tp.channel((0, 1, 2), (0, 1, 1, 3)), good) == -1
+    e = _events(tp)
+    e.p[5] = None
+    assert rc_bin(e, ch, good) == -1
+    assert rc_bin(_events(tp), ch, good, counts=None) == -1
+    bad_phi = synth.Axis(synth.AXIS_ABSPHI, np.array([1.0, 0.3, 0.5, -1.0]))
+    assert rc_bin(_events(tp), ch, _bn(tp, [bad_phi])) == -1
+    short_phi = synth.Axis(synth.AXIS_ABSPHI, np.array([0.9, 0.0, -1.0]))
+    assert rc_bin(_events(tp), ch, _bn(tp, [short_phi])) == -1
+    bad_mass = synth.Axis(synth.AXIS_MASS, np.array([1.0, 3.0, 2.0]), 0b11)
+    assert rc_bin(_events(tp), ch, _bn(tp, [bad_mass])) == -1
+    one_slot = synth.Axis(synth.AXIS_MASS, np.array([1.0, 2.0]), 0b1)
+    assert rc_bin(_events(tp), ch, _bn(tp, [one_slot])) == -1
+    neg_mass = synth.Axis(synth.AXIS_MASS, np.array([-1.0, 2.0]), 0b11)
+    assert rc_bin(_events(tp), ch, _bn(tp, [neg_mass])) == -1
+    bad_cos = synth.Axis(synth.AXIS_ABSCOS, np.array([0.0, 0.5, 0.9]), 0)
+    assert rc_bin(_events(tp), ch, _bn(tp, [bad_cos])) == -1
+    nan_edge = synth.Axis(synth.AXIS_MASS, np.array([1.0, np.nan, 3.0]), 0b11)
+    assert rc_bin(_events(tp), ch, _bn(tp, [nan_edge])) == -1
+    two_phi = _bn(tp, [synth.absphi_axis(4), synth.absphi_axis(4)])
+    assert rc_bin(_events(tp), ch, two_phi) == -1
+    big = _bn(tp, [synth.mass_axis((0, 1), 0, 1, 64), synth.mass_axis((2, 3), 0, 1, 32)])
+    assert rc_bin(_events(tp), ch, big) == -5
+    assert b"1024" in lib.tp_strerror(-5)
+    # tp_compute needs cls_out; tp_batch checks its list
+    assert lib.tp_compute(ctypes.byref(_events(tp)), ctypes.byref(ch), 0, None, None, st, None) == -1
+    assert lib.tp_batch(None, 3, 0, None, 0, None) == -1
+    assert lib.tp_batch(None, 0, 0, None, 4, None) == -1
+    assert lib.tp_asym(None, 1, None) == -1
+    assert lib.tp_scp(None, 1, 0, None, None, None, None) == -1

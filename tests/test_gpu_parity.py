@@ -1,0 +1,222 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle.
+
+Counts and statistics must be bit-exact; asymmetries within 1e-12 relative.
+Sizes are small enough for the oracle to finish in seconds while spanning many
+tiles, several workgroups and ragged tails.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import exact
+from paper_1612_04705_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tp():
+    from paper_1612_04705_amd import tpasym
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    tpasym.load()
+    return tpasym
+
+
+def u64(t):
+    return t.cpu().numpy().view(np.uint64).astype(object)
+
+
+def gpu_bin(tp, sample, ch, axes, prec, tuning=None, graph=False):
+    ds = tp.DeviceSample.from_sample(sample)
+    bn = tp.Binning(axes)
+    counts, stats = tp.new_counts(bn)
+    if tuning is None and not graph:
+        tp.bin(ds, tp.channel(ch.triple, ch.planes), bn, prec, counts, stats)
+    else:
+        b = tp.Batch([(ds, tp.channel(ch.triple, ch.planes), bn, counts, stats)])
+        b.run(prec, tuning, graph)
+    torch.cuda.synchronize()
+    c = [int(x) for x in u64(counts)]
+    return [c[4 * r:4 * r + 4] for r in range(bn.nrows)], [int(x) for x in u64(stats)]
+
+
+def check(tp, sample, ch, axes, precisions=None, label=""):
+    comps, tag = sample.numpy()
+    want = oracle.run(comps, tag, ch.triple, ch.planes, axes)
+    if precisions is None:
+        precisions = [tp.TP_PREC_F64] + ([tp.TP_PREC_F32_RECHECK] if comps.dtype == np.float32 else [])
+    out = []
+    for prec in precisions:
+        counts, stats = gpu_bin(tp, sample, ch, axes, prec)
+        print(f"[parity] {label} prec={prec} n={sample.n} stats={stats}", flush=True)
+        assert stats[6] == 0, "unresolved events"
+        assert counts == want["counts"], label
+        assert stats[:4] == want["stats"], label
+        out.append((counts, stats))
+    return want, out
+
+
+@pytest.mark.parametrize("config,scale", [(1, 0.2), (2, 0.003), (3, 0.0004), (5, 0.0001)])
+def test_config_shapes(tp, config, scale):
+    for spec in synth.config_specs(config, scale):
+        s = synth.make_sample(spec)
+        check(tp, s, spec.channel, spec.axes, label=f"config{config}")
+
+
+def test_batch_config4_shape(tp):
+    specs = synth.config_specs(4, 0.002)
+    items, wants = [], []
+    for spec in specs:
+        s = synth.make_sample(spec)
+        comps, tag = s.numpy()
+        wants.append(oracle.run(comps, tag, spec.channel.triple, spec.channel.planes, spec.axes))
+        ds = tp.DeviceSample.from_sample(s)
+        bn = tp.Binning(spec.axes)
+        counts, stats = tp.new_counts(bn)
+        items.append((ds, tp.channel(spec.channel.triple, spec.channel.planes), bn, counts, stats))
+    b = tp.Batch(items)
+    for prec in (tp.TP_PREC_F32_RECHECK, tp.TP_PREC_F64):
+        for graph, reps in ((False, 1), (True, 3)):
+            for it in items:
+                it[3].zero_()
+                it[4].zero_()
+            for _ in range(reps):
+                b.run(prec, None, graph)
+            torch.cuda.synchronize()
+            for (ds, ch, bn, counts, stats), w in zip(items, wants):
+                c = [int(x) for x in u64(counts)]
+                c = [c[4 * r:4 * r + 4] for r in range(bn.nrows)]
+                st = [int(x) for x in u64(stats)]
+                assert c == [[reps * v for v in row] for row in w["counts"]], (prec, graph)
+                assert st[:4] == [reps * v for v in w["stats"]]
+                assert st[6] == 0
+
+
+def test_compute_per_event_classes(tp):
+    ch = synth.CHANNELS["Lb_ppipipi"]
+    s = synth.generate(ch, 30011, 41)
+    comps, tag = s.numpy()
+    want = oracle.run(comps, tag, ch.triple, ch.planes, want_events=True)
+    ds = tp.DeviceSample.from_sample(s)
+    for prec in (tp.TP_PREC_F64, tp.TP_PREC_F32_RECHECK):
+        cls, ct, stats = tp.compute(ds, tp.channel(ch.triple, ch.planes), prec)
+        torch.cuda.synchronize()
+        g = cls.cpu().numpy()
+        assert np.array_equal(g, want["cls"])
+        ctv = ct.cpu().numpy()
+        ok = want["cls"] < 4
+        # C_T^inv = M * C_T: same sign as the oracle's rest-frame value
+        assert np.array_equal(np.sign(ctv[ok]), np.sign(want["ct"][ok]))
+
+
+def test_asymmetries_from_gpu_counts(tp):
+    spec = synth.config_specs(2, 0.003)[0]
+    s = synth.make_sample(spec)
+    want, outs = check(tp, s, spec.channel, spec.axes)
+    counts = outs[0][0]
+    got = tp.asym(np.array(counts).ravel())
+    for row, g in zip(counts, got):
+        w = exact.asym_row(row)
+        for k in tp.ASYM_KEYS:
+            if w[k][0] is None:
+                assert math.isnan(g[k][0])
+            else:
+                assert abs(g[k][0] - float(w[k][0])) <= 1e-12 * abs(float(w[k][0])) + 1e-300
+                assert abs(g[k][1] - w[k][1]) <= 1e-12 * w[k][1] + 1e-300
+
+
+@pytest.mark.parametrize("n", [1, 3, 4, 63, 64, 65, 255, 1027, 4099])
+def test_ragged_sizes(tp, n):
+    ch = synth.CHANNELS["Lb_pKpipi"]
+    s = synth.generate(ch, n, 50 + n)
+    check(tp, s, ch, [synth.absphi_axis(10), synth.lb_mass03_axis(ch)], label=f"n={n}")
+
+
+def test_unaligned_views_take_scalar_path(tp):
+    ch = synth.CHANNELS["Lb_pKpipi"]
+    s = synth.generate(ch, 5001, 60)
+    axes = [synth.absphi_axis(10), synth.lb_mass03_axis(ch)]
+    comps, tag = s.numpy()
+    want = oracle.run(comps[:, :, 1:], tag[1:], ch.triple, ch.planes, axes)
+    big = [torch.cat([torch.zeros(1, dtype=t.dtype), t]).cuda() for t in s.arrays()]
+    ds = tp.DeviceSample([t[2:] for t in big], torch.cat([torch.zeros(1, dtype=torch.int8), s.tag]).cuda()[2:])
+    bn = tp.Binning(axes)
+    for prec in (tp.TP_PREC_F64, tp.TP_PREC_F32_RECHECK):
+        counts, stats = tp.bin(ds, tp.channel(ch.triple, ch.planes), bn, prec)
+        torch.cuda.synchronize()
+        c = [int(x) for x in u64(counts)]
+        assert [c[4 * r:4 * r + 4] for r in range(bn.nrows)] == want["counts"]
+
+
+def test_adversarial_inputs(tp):
+    from test_oracle_pins import _load_handbuilt, _as_sample
+    rows = _load_handbuilt()
+    hb, hbt = _as_sample(rows)
+    ch = synth.CHANNELS["Lb_pKpipi"]
+    s = synth.generate(ch, 3000, 61)
+    comps, tag = s.numpy()
+    c = comps.copy()
+    t = tag.copy()
+    c[:, 3, :300] = 0.0                         # coplanar -> zero class (exact tier)
+    c[1, 2, 300] = np.nan
+    c[2, 0, 301] = np.inf
+    t[302] = 9
+    c[:, 0, 303] = 0.0                          # no rest frame
+    c[0, 1, 304] = np.float32(1e-30)
+    c[2, :, 305] = c[1, :, 305]                 # two equal daughters -> zero
+    reps = np.concatenate([np.tile(hb, (1, 1, 40)), c], axis=2)
+    rept = np.concatenate([np.tile(hbt, 40), t])
+    samp = synth.Sample(ch, [[torch.from_numpy(np.ascontiguousarray(reps[a, b])) for b in range(4)]
+                             for a in range(4)], torch.from_numpy(rept))
+    for axes in ([synth.absphi_axis(12)], [synth.absphi_axis(10), synth.lb_mass03_axis(ch)],
+                 [synth.abscos_axis(0, 5), synth.absphi_axis(10)],
+                 [synth.Axis(synth.AXIS_MASS, np.array([5.0, 6.0, 7.0, 5000.0]), 0b1001)]):
+        want, outs = check(tp, samp, synth.Channel("t", 0, (0,) * 4, (0, 1, 2)), axes, label="adversarial")
+        for counts, stats in outs:
+            assert stats[5] > 0          # the exact tier was used
+
+
+@pytest.mark.parametrize("gamma", [300.0, 3000.0, 1.0e4])
+def test_high_boost_needs_recheck(tp, gamma):
+    ch = synth.CHANNELS["D0_KKpipi"]
+    s = synth.generate(ch, 20000, 62, fixed_gamma=gamma)
+    want, outs = check(tp, s, ch, [synth.mass_axis((0, 1), 987.354, 1585.7, 32),
+                                   synth.mass_axis((2, 3), 279.14, 877.486, 32)], label=f"gamma={gamma}")
+    # float32 path at high boost needs the float64 recheck of the sign for some events
+    assert outs[1][1][4] > 0
+
+
+def test_tuning_invariance(tp):
+    spec = synth.config_specs(5, 0.00005)[0]
+    s = synth.make_sample(spec)
+    ref = None
+    for block in (256, 512):
+        for wpc in (1, 3, 8):
+            for copies in (1, 2, 4):
+                t = tp.Tuning(block, wpc, copies, 1)
+                got = gpu_bin(tp, s, spec.channel, spec.axes, tp.TP_PREC_F32_RECHECK, tuning=t)
+                if ref is None:
+                    ref = got
+                assert got == ref, t.as_dict()
+
+
+def test_chunked_equals_whole(tp):
+    spec = synth.config_specs(3, 0.0003)[0]
+    s = synth.make_sample(spec)
+    ch = tp.channel(spec.channel.triple, spec.channel.planes)
+    bn = tp.Binning(spec.axes)
+    whole = gpu_bin(tp, s, spec.channel, spec.axes, tp.TP_PREC_F32_RECHECK)
+    counts, stats = tp.new_counts(bn)
+    ds = tp.DeviceSample.from_sample(s)
+    n = ds.n
+    cuts = [0, 7, 4096, 10001, n // 2 + 3, n]
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        part = tp.DeviceSample([t[a:b] for t in ds.comps], ds.tag[a:b])
+        tp.bin(part, ch, bn, tp.TP_PREC_F32_RECHECK, counts, stats)
+    torch.cuda.synchronize()
+    c = [int(x) for x in u64(counts)]
+    assert [c[4 * r:4 * r + 4] for r in range(bn.nrows)] == whole[0]
+    assert [int(x) for x in u64(stats)][:4] == whole[1][:4]
