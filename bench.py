@@ -1,0 +1,246 @@
+"""Benchmark of the T-odd triple-product asymmetry pass on one MI355X.
+
+Workload (default): the batched workload -- 64 independent samples, sizes
+log-uniform in [1e3, 1e7] events, four Lambda_b channels x three binning
+schemes (|Phi|; |Phi| x m(0,3); |cos theta_p| x |Phi|), float32 SoA storage,
+all in one persistent launch captured in a HIP graph, tuned by the autotuner.
+One step = one pass of the whole hot path over the whole batch (every event:
+contraction, certified sign, class, bins, histogram, flush; the exact tier's
+list pass).  Inputs are generated on the GPU before timing and stay in HBM.
+
+Prints ONE JSON line (see the roofline / cpu_baseline objects).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_F32 = 65      # 16 x 4 B components + 1 B tag per event
+BYTES_F64 = 129
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("tp_pass.hip", "tp_kernel.h"):
+        with open(os.path.join(ROOT, "paper_1612_04705_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    fn = os.path.join(ROOT, "profiles", "tp_pass_kernel_counters.json")
+    if not os.path.exists(fn):
+        return None
+    with open(fn) as f:
+        d = json.load(f)
+    e = d.get(workload)
+    if not e or e.get("source_hash") != source_hash():
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
+def make_workload(config, device, scale):
+    import torch
+    from paper_1612_04705_amd import synth, tpasym
+    specs = synth.config_specs(config, scale)
+    items, samples = [], []
+    t0 = time.time()
+    for spec in specs:
+        s = synth.make_sample(spec, device=device)
+        ds = tpasym.DeviceSample([s.comps[a][b] for a in range(4) for b in range(4)], s.tag)
+        bn = tpasym.Binning(spec.axes)
+        counts, stats = tpasym.new_counts(bn, device)
+        items.append((ds, tpasym.channel(spec.channel.triple, spec.channel.planes), bn, counts, stats))
+        samples.append((spec, s))
+    torch.cuda.synchronize()
+    log(f"generated {len(specs)} samples, {sum(s.n for _, s in samples)} events in {time.time() - t0:.1f}s")
+    return specs, samples, items
+
+
+def cpu_baseline(samples, budget_events, want_counts_of):
+    """Time the oracle (float64 pass + exact resolution) on the first whole samples
+    up to ``budget_events`` events; return the cpu_baseline object and the
+    oracle counts per sample index for the parity check."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    nthreads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    done, secs, used = 0, 0.0, []
+    out = {}
+    for i, (spec, s) in enumerate(samples):
+        if done > 0 and done + s.n > budget_events:
+            continue
+        comps = np.stack([s.comps[a][b].cpu().numpy() for a in range(4) for b in range(4)]).reshape(4, 4, -1)
+        tag = s.tag.cpu().numpy()
+        t0 = time.perf_counter()
+        r = oracle.run(comps, tag, spec.channel.triple, spec.channel.planes, spec.axes, nthreads=nthreads)
+        secs += time.perf_counter() - t0
+        done += s.n
+        used.append(i)
+        if i in want_counts_of:
+            out[i] = r
+        if done >= budget_events:
+            break
+    try:
+        model = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
+    except Exception:
+        model = "unknown"
+    return {"value": done / secs, "unit": "events/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{len(used)} whole samples of the same workload ({done} events; float64 pass + exact "
+                      f"resolution of flagged events; {model})",
+            "seconds": secs}, out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=4)
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--cpu-events", type=float, default=6e6)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the pass shards by events with one uint64 histogram all-reduce; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1612_04705_amd import tpasym
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    tpasym.load()
+    prec = tpasym.TP_PREC_F32_RECHECK if args.precision == "f32" else tpasym.TP_PREC_F64
+    specs, samples, items = make_workload(args.config, dev, args.scale)
+    nevents = sum(s.n for _, s in samples)
+    f64_store = samples[0][1].comps[0][0].dtype == torch.float64
+    bpe = BYTES_F64 if f64_store else BYTES_F32
+    batch = tpasym.Batch(items)
+    stream = torch.cuda.current_stream()
+
+    tuning = None
+    if not args.no_autotune:
+        t0 = time.time()
+        tuning = batch.autotune(prec)
+        log(f"autotune: {tuning.as_dict()} in {time.time() - t0:.1f}s")
+    graph = not args.no_graph
+    for _ in range(args.warmup):
+        batch.run(prec, tuning, graph)
+    torch.cuda.synchronize()
+
+    tpasym.timing_enable(True)
+    tpasym.timing_reset()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for k in range(args.steps):
+        batch.run(prec, tuning, graph)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    kern_ms, launches = tpasym.timing_read()
+    tpasym.timing_enable(False)
+    ms_per_step = total_ms / args.steps
+    value = nevents / (ms_per_step / 1e3)
+    log(f"{args.steps} steps: {ms_per_step:.4f} ms/step, kernel {kern_ms:.4f} ms over {launches} launches")
+
+    # statistics and parity-relevant totals (counts accumulate over warmup + steps)
+    reps = args.warmup + args.steps
+    st = np.stack([it[4].cpu().numpy().view(np.uint64) for it in items]).astype(np.float64).sum(axis=0)
+    tier2, tier3, unres = st[4] / reps, st[5] / reps, st[6] / reps
+
+    # plain all-float64 single-sample path, same inputs (non-persistent per-sample launches)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    f64_items = [(ds, ch, bn, *tpasym.new_counts(bn, dev)) for ds, ch, bn, _, _ in items]
+    for ds, ch, bn, c, s in f64_items:
+        tpasym.bin(ds, ch, bn, tpasym.TP_PREC_F64, c, s)
+    torch.cuda.synchronize()
+    f64_steps = max(3, args.steps // 4)
+    t0.record(stream)
+    for _ in range(f64_steps):
+        for ds, ch, bn, c, s in f64_items:
+            tpasym.bin(ds, ch, bn, tpasym.TP_PREC_F64, c, s)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    f64_ms = t0.elapsed_time(t1) / f64_steps
+    # both paths must agree bit for bit
+    agree = all(np.array_equal(a[3].cpu().numpy().view(np.uint64) // reps,
+                               b[3].cpu().numpy().view(np.uint64) // (f64_steps + 1))
+                for a, b in zip(items, f64_items))
+
+    wl = {1: "config1_Lb_ppipipi_f64_1e5", 2: "config2_Lb_ppipipi_1e7_12phi",
+          3: "config3_Lb_pKpipi_1e8_10phix8m", 4: "config4_batched_64_samples",
+          5: "config5_D0_KKpipi_5e8_32x32m"}[args.config]
+    if args.scale != 1.0:
+        wl += f"_scale{args.scale:g}"
+    achieved = nevents * bpe / (kern_ms / 1e3) / 1e9 if kern_ms > 0 else None
+    traffic = traffic_from_profiles(wl)
+    out = {
+        "metric": "events/s for triple-product asymmetry pass; % of HBM peak; vs plain FP64 path",
+        "value": value,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == tpasym.TP_PREC_F32_RECHECK and not f64_store else "f64",
+        "data": "synthetic",
+        "config": {"workload": wl, "samples": len(samples), "events": nevents,
+                   "storage": "f64" if f64_store else "f32",
+                   "path": ("persistent batched pass, HIP graph" if graph else "persistent batched pass"),
+                   "precision": args.precision, "tuning": tuning.as_dict() if tuning else None},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS if achieved else None,
+                     "traffic": traffic,
+                     "bytes_per_event": bpe, "kernel_ms": kern_ms, "kernel_launches": launches},
+        "fp64_single_sample": {"value": nevents / (f64_ms / 1e3), "unit": "events/s", "ms_per_step": f64_ms,
+                               "counts_equal_fast_path": bool(agree)},
+        "tiers": {"tier2_per_step": tier2, "tier3_per_step": tier3, "unresolved_per_step": unres},
+        "paper_context": "energy test (different algorithm): 1e6 events, one permutation ~30 min on "
+                         "NVIDIA M2070 / K40c (Sect. 6); no timing is given for the triple-product pass",
+    }
+    if not args.no_cpu:
+        want = {}
+        cpu, orc = cpu_baseline(samples, args.cpu_events, set(range(len(samples))))
+        out["cpu_baseline"] = {k: v for k, v in cpu.items() if k != "seconds"}
+        ok = True
+        for i, r in orc.items():
+            c = items[i][3].cpu().numpy().view(np.uint64)
+            if not np.all(c % reps == 0):
+                ok = False
+                continue
+            got = (c // reps).astype(np.int64).tolist()
+            wantc = [v for row in r["counts"] for v in row]
+            ok = ok and got == wantc
+        out["parity_vs_oracle"] = {"samples_checked": len(orc), "counts_bit_exact": bool(ok)}
+        log(f"cpu baseline {cpu['value']:.3e} events/s on {cpu['cores']} threads ({cpu['seconds']:.1f}s)")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -398,7 +398,7 @@ __device__ __forceinline__ Tin ld(const void *p, int64_t i)
 }
 
 template <typename Tin, int PREC, int MODE>
-__global__ __launch_bounds__(256) void tp_pass_kernel(const KParams kp)
+__global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
 {
     constexpr int EPL = sizeof(Tin) == 4 ? 4 : 2;   // events per lane per step (16-byte loads)
     extern __shared__ __align__(16) unsigned char smem[];
