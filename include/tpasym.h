@@ -212,7 +212,8 @@ typedef struct {
     int32_t block;          /* threads per workgroup: 256 or 512                    */
     int32_t wg_per_cu;      /* persistent workgroups per compute unit: 1..16        */
     int32_t lds_copies;     /* LDS histogram copies per workgroup: 1 .. waves/WG    */
-    int32_t unroll;         /* vector loads in flight per lane per step: 1 or 2      */
+    int32_t unroll;         /* events per lane per step: 1, 2 or 4 (float32 storage;
+                               float64 storage uses at most 2)                       */
 } tp_tuning;
 
 #define TP_BATCH_GRAPH 1    /* capture the launch in a HIP graph on first use and replay it */

@@ -223,6 +223,10 @@ TP_HD inline int cmp_scaled(const Big<NA> &a, int sa, const Big<NB> &b, int sb, 
     return mag_cmp(x, y);
 }
 
+// sign(x - y * sqrt(r2)) as cmp_sqrt, with x2 = x^2 precomputed.
+template <int NX, int NX2, int NR>
+TP_HD inline int cmp_sqrt_x2(const Big<NX> &x, const Big<NX2> &x2, const Big<NR> &r2, double y, bool &ok);
+
 // ------------------------------------------------------------- float decoding
 // x = mant * 2^exp exactly, mant an integer with |mant| < 2^53 (0 for zero)
 TP_HD inline void decode_f64(double x, int64_t &mant, int &exp)
@@ -393,6 +397,22 @@ TP_HD inline int cmp_sqrt(const Big<NX> &x, const Big<NR> &r2, double y, bool &o
     // same strict sign: compare x^2 with y^2 r2
     Big<2 * NX> x2;
     ok = ok && big_mul(x2, x, x);
+    return cmp_sqrt_x2(x, x2, r2, y, ok);
+}
+
+template <int NX, int NX2, int NR>
+TP_HD inline int cmp_sqrt_x2(const Big<NX> &x, const Big<NX2> &x2in, const Big<NR> &r2, double y, bool &ok)
+{
+    int64_t ym;
+    int ye;
+    decode_f64(y, ym, ye);
+    const int sx = big_sign(x);
+    const int sy = ym > 0 ? 1 : (ym < 0 ? -1 : 0);
+    const int sr = big_sign(r2);
+    if (sx >= 0 && (sy <= 0 || sr == 0)) return (sx == 0 && (sy == 0 || sr == 0)) ? 0 : 1;
+    if (sx <= 0 && (sy >= 0 || sr == 0)) return (sx == 0 && (sy == 0 || sr == 0)) ? 0 : -1;
+    Big<NX2> x2;
+    big_copy(x2, x2in);
     const uint64_t am = ym < 0 ? (uint64_t)(-ym) : (uint64_t)ym;
     // am^2 < 2^106: compute as 128-bit
     const uint64_t lo32 = am & 0xffffffffu, hi32 = am >> 32;
@@ -459,10 +479,10 @@ TP_HD inline int decide(const int64_t mant[4][4], const int ex[4][4], bool finit
                 ev.ok = ev.ok && big_mul(t1, G02, G13) && big_mul(t2, G03, G12) && big_addsub(X, t1, t2, -1);
                 ev.ok = ev.ok && big_mul(t1, G00, G11) && big_mul(t2, G01, G01) && big_addsub(N1, t1, t2, -1);
                 ev.ok = ev.ok && big_mul(t1, G22, G33) && big_mul(t2, G23, G23) && big_addsub(N2, t1, t2, -1);
-                Big<L16> R2;
-                ev.ok = ev.ok && big_mul(R2, N1, N2);
+                Big<L16> R2, X2;
+                ev.ok = ev.ok && big_mul(R2, N1, N2) && big_mul(X2, X, X);
                 for (int k = 1; k < nb; ++k)
-                    if (cmp_sqrt(X, R2, ed[k], ev.ok) <= 0) ++j;
+                    if (cmp_sqrt_x2(X, X2, R2, ed[k], ev.ok) <= 0) ++j;
             } else if (kind[a] == X_ABSCOS) {
                 // |cos theta| >= e_k  <=>  sign(|Nn| - e_k sqrt(A B)) >= 0
                 const int sl = slots[a];
@@ -473,10 +493,12 @@ TP_HD inline int decide(const int64_t mant[4][4], const int ex[4][4], bool finit
                 ev.ok = ev.ok && event_G(ev, sl, sl, A);
                 ev.ok = ev.ok && big_mul(dd, ev.P[0], ev.P[0]) && big_addsub(Bv, dd, ev.M2, -1);
                 Big<L4 + L2> AB;
+                Big<2 * L4> Nn2;
                 ev.ok = ev.ok && big_mul(AB, A, Bv);
                 Nn.neg = 0;
+                ev.ok = ev.ok && big_mul(Nn2, Nn, Nn);
                 for (int k = 1; k < nb; ++k)
-                    if (cmp_sqrt(Nn, AB, ed[k], ev.ok) >= 0) ++j;
+                    if (cmp_sqrt_x2(Nn, Nn2, AB, ed[k], ev.ok) >= 0) ++j;
             } else {
                 // m >= e_k  <=>  m^2 >= e_k^2 (e_k >= 0); m^2 < 0 lies below every edge
                 const int mask = slots[a];

@@ -1,11 +1,13 @@
-// Exact tier of the T-odd pass: the events the floating-point tiers could not
-// decide, taken from the work list and decided in exact integer arithmetic
-// (tp_exact.h): validity, sign of the triple product (Sect. 5, eq. (4)) and
-// every bin-edge comparison.  Results are added to the sample's counters with
+// Last tiers of the T-odd pass: the events the float64 tier could not decide,
+// taken from the work list and decided first in certified double-word
+// arithmetic (tp_dword.h) and, if that does not settle them, in exact integer
+// arithmetic (tp_exact.h): validity, sign of the triple product (Sect. 5,
+// eq. (4)) and every bin-edge comparison.  Results are added to the sample's counters with
 // device-scope atomics; the last workgroup clears the list for the next launch.
 #include <hip/hip_runtime.h>
 
 #define TP_HD __host__ __device__
+#include "tp_dword.h"
 #include "tp_exact.h"
 #include "tp_kernel.h"
 
@@ -22,26 +24,35 @@ __global__ __launch_bounds__(64) void tp_exact_kernel(const KParams kp)
     const uint32_t n = cnt < kp.xcap ? cnt : kp.xcap;
     for (uint32_t it = blockIdx.x * blockDim.x + threadIdx.x; it < n; it += gridDim.x * blockDim.x) {
         const uint64_t ent = kp.xlist[it];
-        const int s = (int)(ent >> 40);
+        const int s = (int)((ent >> 40) & 0xfffff);
         const int64_t i = (int64_t)(ent & ((1ull << 40) - 1));
         const KSample &S = kp.samples[s];
         const int tag = S.tag[i];
-        int64_t mant[4][4];
-        int ex[4][4];
+        double xv[4][4];
         bool finite = true;
         for (int k = 0; k < 4; ++k)
             for (int c = 0; c < 4; ++c) {
-                const Tin v = reinterpret_cast<const Tin *>(S.p[k * 4 + c])[i];
-                if (!isfinite((double)v)) finite = false;
-                if constexpr (sizeof(Tin) == 4) tpx::decode_f32((float)v, mant[k][c], ex[k][c]);
-                else tpx::decode_f64((double)v, mant[k][c], ex[k][c]);
+                xv[k][c] = (double)reinterpret_cast<const Tin *>(S.p[k * 4 + c])[i];
+                if (!isfinite(xv[k][c])) finite = false;
             }
         const double *eds[2] = { nullptr, nullptr };
         for (int a = 0; a < S.naxes && a < 2; ++a)
             eds[a] = kp.edges + S.eoff[a] + (S.kind[a] == AX_MASS ? 2 * (S.nbins[a] + 1) : 0);
+        const int nax = MODE == 0 ? S.naxes : 0;
         int bin = -1;
-        int cls = tpx::decide(mant, ex, finite, tag, sizeof(Tin) == 4 ? 136 : 107, S.sigma,
-                              MODE == 0 ? S.naxes : 0, S.kind, S.nbins, S.slots, eds, bin);
+        int cls = finite ? tpw::decide_dw(xv, tag, S.sigma, nax, S.kind, S.nbins, S.slots, eds, bin)
+                         : (int)tpw::W_UNCERTAIN;
+        if (cls == tpw::W_UNCERTAIN) {
+            int64_t mant[4][4];
+            int ex[4][4];
+            for (int k = 0; k < 4; ++k)
+                for (int c = 0; c < 4; ++c) {
+                    if constexpr (sizeof(Tin) == 4) tpx::decode_f32((float)xv[k][c], mant[k][c], ex[k][c]);
+                    else tpx::decode_f64(xv[k][c], mant[k][c], ex[k][c]);
+                }
+            cls = tpx::decide(mant, ex, finite, tag, sizeof(Tin) == 4 ? 136 : 107, S.sigma, nax, S.kind,
+                              S.nbins, S.slots, eds, bin);
+        }
         const bool unres = cls == CLS_UNRESOLVED;
         if (MODE == 1) {
             S.cls_out[i] = (int8_t)cls;

@@ -19,7 +19,7 @@
 #include "tp_kernel.h"
 
 namespace tpk {
-hipError_t launch_pass(int dtype, int prec, int mode, const KParams &kp, int grid, int block,
+hipError_t launch_pass(int dtype, int prec, int mode, int epl, const KParams &kp, int grid, int block,
                        size_t lds, hipStream_t st);
 hipError_t launch_exact(int dtype, int mode, const KParams &kp, int grid, hipStream_t st);
 }  // namespace tpk
@@ -412,7 +412,7 @@ void defaults(Device &d, tp_tuning &t, int64_t vtotal)
     if (t.wg_per_cu < 1 || t.wg_per_cu > 16) t.wg_per_cu = 4;
     const int waves = t.block / 64;
     if (t.lds_copies < 1 || t.lds_copies > waves) t.lds_copies = waves;
-    if (t.unroll < 1 || t.unroll > 2) t.unroll = 1;
+    if (t.unroll != 1 && t.unroll != 2 && t.unroll != 4) t.unroll = 1;
     (void)d;
     (void)vtotal;
 }
@@ -423,7 +423,7 @@ int launch_plan(Device &d, const Plan &p, const tp_tuning &tu_in, int prec, int 
     tp_tuning tu = tu_in;
     defaults(d, tu, p.vtotal);
     if (p.vtotal == 0) return TP_OK;
-    const int epl = p.dtype == TP_F32 ? 4 : 2;
+    const int epl = p.dtype == TP_F32 ? tu.unroll : std::min(tu.unroll, 2);
     int copies = tu.lds_copies;
     size_t hist_bytes = 0;
     for (;;) {
@@ -464,11 +464,29 @@ int launch_plan(Device &d, const Plan &p, const tp_tuning &tu_in, int prec, int 
         e1 = pr.second;
         TP_HIP(hipEventRecord(e0, st));
     }
-    TP_HIP(launch_pass(p.dtype, prec, mode, kp, (int)grid, tu.block, lds, st));
+    TP_HIP(launch_pass(p.dtype, prec, mode, epl, kp, (int)grid, tu.block, lds, st));
     if (timed) {
         TP_HIP(hipEventRecord(e1, st));
         g_timing.next = (g_timing.next + 1) % g_timing.ring.size();
         g_timing.used = std::min(g_timing.used + 1, g_timing.ring.size());
+    }
+    static const bool debug = std::getenv("TP_DEBUG") != nullptr;
+    if (debug) {
+        // diagnostics: which events the float64 tier deferred, and at which stage
+        uint32_t cnt = 0;
+        TP_HIP(hipStreamSynchronize(st));
+        TP_HIP(hipMemcpy(&cnt, ws.xcount, sizeof cnt, hipMemcpyDeviceToHost));
+        const uint32_t m = std::min<uint32_t>(cnt, 4096);
+        std::vector<uint64_t> lst(m);
+        if (m) TP_HIP(hipMemcpy(lst.data(), ws.xlist, m * sizeof(uint64_t), hipMemcpyDeviceToHost));
+        int why[5] = { 0, 0, 0, 0, 0 };
+        for (uint64_t e : lst) why[std::min<int>(4, (int)(e >> 60))]++;
+        std::fprintf(stderr, "tp_debug: %u deferred (validity %d, sign %d, axis0 %d, axis1 %d)", cnt, why[1],
+                     why[2], why[3], why[4]);
+        for (uint32_t k = 0; k < std::min<uint32_t>(m, 8); ++k)
+            std::fprintf(stderr, " [s%d e%lld w%d]", (int)((lst[k] >> 40) & 0xfffff),
+                         (long long)(lst[k] & ((1ull << 40) - 1)), (int)(lst[k] >> 60));
+        std::fprintf(stderr, "\n");
     }
     TP_HIP(launch_exact(p.dtype, mode, kp, EXACT_GRID, st));
     return TP_OK;
@@ -775,15 +793,16 @@ int tp_autotune(const tp_sample *samples, int32_t nsamples, int32_t precision, v
     }
     for (auto &s : sink) rq.push_back(Req{ &s.ev, &s.ch, &s.bn, s.counts, s.stats, nullptr, nullptr });
     std::vector<tp_tuning> cand;
-    for (int wpc : { 1, 2, 4, 8 })
-        for (int copies : { 1, 2, 4 }) {
-            tp_tuning t;
-            t.block = 256;
-            t.wg_per_cu = wpc;
-            t.lds_copies = copies;
-            t.unroll = 1;
-            cand.push_back(t);
-        }
+    for (int epl : { 1, 2, 4 })
+        for (int wpc : { 2, 4, 8 })
+            for (int copies : { 1, 4 }) {
+                tp_tuning t;
+                t.block = 256;
+                t.wg_per_cu = wpc;
+                t.lds_copies = copies;
+                t.unroll = epl;
+                cand.push_back(t);
+            }
     hipEvent_t a, b;
     TP_HIP(hipEventCreate(&a));
     TP_HIP(hipEventCreate(&b));

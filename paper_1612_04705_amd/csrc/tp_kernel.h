@@ -47,7 +47,7 @@ struct KParams {
     int64_t range;            // virtual events per workgroup (multiple of 4)
     int64_t vtotal;           // total virtual events
     const double *edges;      // edge table
-    uint64_t *xlist;          // exact-tier work list: (sample << 40) | event
+    uint64_t *xlist;          // deferred events: (stage << 60) | (sample << 40) | event
     uint32_t *xcount;         // number of listed events
     uint32_t *xdone;          // finished exact-tier workgroups (last one resets)
     uint32_t xcap;

@@ -36,6 +36,7 @@ struct EvOut {
     int cls;      // CLS_* (CLS_DEFER: exact tier)
     int bin;      // combined bin, -1 out of range
     int t2;       // float64 recheck of the sign was needed
+    int why;      // deferred at: 1 validity, 2 sign, 3 first axis, 4 second axis
     double ct;    // C_T^inv estimate
 };
 
@@ -121,84 +122,96 @@ __device__ __forceinline__ double mink(const double a[4], const double b[4])
     return fma(-a[3], b[3], fma(-a[2], b[2], fma(-a[1], b[1], a[0] * b[0])));
 }
 
-// Bin of the plane angle between kernel planes (0,1) and (2,3).
-// edges: c_0 = 1 > c_1 > ... > c_n = -1; returns #{k in 1..n-1 : cos Phi <= c_k}.
-__device__ __forceinline__ int bin_absphi(const double x[4][4], const double w[4], double W,
-                                          double M2, double eM, double kdot,
-                                          const double *edges, int n, bool &sure)
+__device__ __forceinline__ double dmax(double a, double b) { return __builtin_fmax(a, b); }
+
+// 1/sqrt(D), D > 0: hardware estimate r0, one Newton step, and the residual
+// rho = 1 - D r0^2 of the estimate.  With |rho| <= 2^-10 the result satisfies
+// |r sqrt(D) - 1| <= 0.5 rho^2 + 3u  (Newton's error is 1.5 delta^2 for an
+// estimate error delta, and |rho| >= 1.9 |delta|).  ``rel`` receives that bound.
+__device__ __forceinline__ double rsqrt_cert(double D, double &rel, bool &ok)
 {
-    double d[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = a; b < 4; ++b) {
-            d[a][b] = mink(x[a], x[b]);
-            d[b][a] = d[a][b];
-        }
-    double PP[4], Ua[4], Va[4], Ta[4], V2a[4];
-    const double uW = (7.2 * U64) * W;
+    const double r0 = __builtin_amdgcn_rsq(D);
+    const double t = D * r0;
+    const double rho = fma(-t, r0, 1.0);
+    const double r = fma(0.5 * r0, rho, r0);
+    ok = ok && (dabs(rho) <= 0x1p-10);
+    rel = fma(0.5 * rho, rho, 3.0 * U64);
+    return r;
+}
+
+// Error bound of v = Y * r against the true ratio Y / sqrt(D) when |Y| <= sqrt(D)
+// holds exactly: eY, eD bound |Y^ - Y| and |D^ - D| (eD <= D^/4), rel bounds
+// |r sqrt(D^) - 1|.  Includes the rounding of v and of the later v +- eps.
+__device__ __forceinline__ double ratio_eps(double v, double r, double rel, double eY, double eD)
+{
+    return fma(1.01, fma(dabs(v), rel + U64, fma(eY, r, 0.54 * eD * r * r)), 3.0 * U64);
+}
+
+// Plane angle between kernel planes (0,1) and (2,3): cos Phi = X / sqrt(N1 N2).
+// edges: c_0 = 1 > c_1 > ... > c_n = -1; returns #{k in 1..n-1 : cos Phi <= c_k}.
+// Error bounds: |P.p_a^ - P.p_a| <= 7.2 u W w_a, |M^2^ - M^2| <= 10.2 u W^2,
+// |d_ab^ - d_ab| <= kdot u w_a w_b (w_a = L1 norm of p_a, W = sum of w_a); one
+// bound eG serves every G_ab, built from the largest |P.p_a|, |d_ab| and w_a.
+__device__ __forceinline__ int bin_absphi(const double x[4][4], double W, double wmax, double M2,
+                                          double kdot, const double *edges, int n, bool &sure)
+{
+    const double d00 = mink(x[0], x[0]), d11 = mink(x[1], x[1]), d22 = mink(x[2], x[2]), d33 = mink(x[3], x[3]);
+    const double d01 = mink(x[0], x[1]), d02 = mink(x[0], x[2]), d03 = mink(x[0], x[3]);
+    const double d12 = mink(x[1], x[2]), d13 = mink(x[1], x[3]), d23 = mink(x[2], x[3]);
+    const double P0 = (d00 + d01) + (d02 + d03);
+    const double P1 = (d01 + d11) + (d12 + d13);
+    const double P2 = (d02 + d12) + (d22 + d23);
+    const double P3 = (d03 + d13) + (d23 + d33);
+#define TP_G(a, b, dab) fma(P##a, P##b, -(M2 * dab))
+    const double G00 = TP_G(0, 0, d00), G11 = TP_G(1, 1, d11), G22 = TP_G(2, 2, d22), G33 = TP_G(3, 3, d33);
+    const double G01 = TP_G(0, 1, d01), G23 = TP_G(2, 3, d23);
+    const double G02 = TP_G(0, 2, d02), G13 = TP_G(1, 3, d13), G03 = TP_G(0, 3, d03), G12 = TP_G(1, 2, d12);
+#undef TP_G
+    const double PPm = dmax(dmax(dabs(P0), dabs(P1)), dmax(dabs(P2), dabs(P3)));
+    const double dm = dmax(dmax(dmax(dabs(d00), dabs(d11)), dmax(dabs(d22), dabs(d33))),
+                           dmax(dmax(dmax(dabs(d01), dabs(d02)), dmax(dabs(d03), dabs(d12))),
+                                dmax(dabs(d13), dabs(d23))));
     const double aM = dabs(M2);
-    const double tM = (kdot * U64) * aM;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        PP[a] = (d[a][0] + d[a][1]) + (d[a][2] + d[a][3]);
-        Ua[a] = uW * w[a];                 // error bound of P.p_a
-        Va[a] = dabs(PP[a]);
-        Ta[a] = tM * w[a];
-        V2a[a] = (2.01 * U64) * Va[a];
-    }
     const double uWW = U64 * W * W;
-    const double cd = fma(10.2, uWW, (2.01 * U64) * aM);
-    const double c2 = 94.0 * uWW * uWW;
-    double G[4][4], eG[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = a; b < 4; ++b) {
-            G[a][b] = fma(PP[a], PP[b], -(M2 * d[a][b]));
-            eG[a][b] = fma(Ua[a], Va[b], fma(Ua[b], Va[a], fma(cd, dabs(d[a][b]),
-                          fma(Ta[a], w[b], fma(V2a[a], Va[b], c2)))));
-        }
-    (void)eM;
+    // eG >= |G^ - G| for every pair (first-order terms, second-order 94 u^2 W^4, roundings)
+    const double eG = fma(U64, fma((14.4 * W) * wmax, PPm, fma(10.2 * W * W, dm,
+                          fma((kdot * wmax) * wmax, aM, 2.01 * fma(PPm, PPm, aM * dm)))),
+                          94.0 * uWW * uWW);
     const double u2 = 2.01 * U64;
-    // X = G02 G13 - G03 G12 ; N1 = G00 G11 - G01^2 ; N2 = G22 G33 - G23^2
-    const double X = fma(G[0][2], G[1][3], -(G[0][3] * G[1][2]));
-    const double eX = fma(dabs(G[0][2]) + eG[0][2], eG[1][3],
-                      fma(dabs(G[1][3]), eG[0][2],
-                      fma(dabs(G[0][3]) + eG[0][3], eG[1][2],
-                      fma(dabs(G[1][2]), eG[0][3],
-                          u2 * (dabs(G[0][2] * G[1][3]) + dabs(G[0][3] * G[1][2]))))));
-    const double N1 = fma(G[0][0], G[1][1], -(G[0][1] * G[0][1]));
-    const double eN1 = fma(dabs(G[0][0]) + eG[0][0], eG[1][1],
-                       fma(dabs(G[1][1]), eG[0][0],
-                       fma(2.0 * dabs(G[0][1]) + eG[0][1], eG[0][1],
-                           u2 * (dabs(G[0][0] * G[1][1]) + G[0][1] * G[0][1]))));
-    const double N2 = fma(G[2][2], G[3][3], -(G[2][3] * G[2][3]));
-    const double eN2 = fma(dabs(G[2][2]) + eG[2][2], eG[3][3],
-                       fma(dabs(G[3][3]), eG[2][2],
-                       fma(2.0 * dabs(G[2][3]) + eG[2][3], eG[2][3],
-                           u2 * (dabs(G[2][2] * G[3][3]) + G[2][3] * G[2][3]))));
+    const double p1 = G03 * G12;
+    const double X = fma(G02, G13, -p1);
+    const double eX = fma(eG, ((dabs(G02) + dabs(G13)) + (dabs(G03) + dabs(G12))) + 2.0 * eG,
+                          u2 * fma(dabs(G02), dabs(G13), dabs(p1)));
+    const double q1 = G01 * G01;
+    const double N1 = fma(G00, G11, -q1);
+    const double eN1 = fma(eG, (dabs(G00) + dabs(G11)) + (2.0 * dabs(G01) + 2.0 * eG),
+                           u2 * fma(dabs(G00), dabs(G11), q1));
+    const double q2 = G23 * G23;
+    const double N2 = fma(G22, G33, -q2);
+    const double eN2 = fma(eG, (dabs(G22) + dabs(G33)) + (2.0 * dabs(G23) + 2.0 * eG),
+                           u2 * fma(dabs(G22), dabs(G33), q2));
     bool ok = (N1 > eN1) && (N2 > eN2);
     const double D = N1 * N2;
     const double eD = fma(N1 + eN1, eN2, fma(N2, eN1, U64 * D));
     ok = ok && (eD <= 0.25 * D);
-    const double r = 1.0 / sqrt(D);
+    double rel;
+    const double r = rsqrt_cert(D, rel, ok);
     const double v = X * r;
-    // |v - cos Phi| <= eX/s + eD/s^2 + 8.4u (|cos Phi| <= 1), s = sqrt(D)
-    const double eps = fma(1.001, fma(eX, r, eD * r * r), 11.0 * U64);
+    const double eps = ratio_eps(v, r, rel, eX, eD);
+    const double vhi = v + eps, vlo = v - eps;
     int bin = 0;
     for (int k = 1; k < n; ++k) {
         const double c = edges[k];
-        const bool le = (v + eps) <= c;
-        const bool gt = (v - eps) > c;
+        const bool le = vhi <= c;
         bin += le ? 1 : 0;
-        ok = ok && (le || gt);
+        ok = ok && (le || vlo > c);
     }
     sure = sure && ok;
     return bin;
 }
 
-// |cos theta| of kernel slot s against the M flight direction.
+// |cos theta| of kernel slot s against the M flight direction:
+// Nn = (P.p_s) E_P - M^2 E_s, A = G_ss, B = |P_lab|^2, |cos| = |Nn| / sqrt(A B).
 // edges 0 = e_0 < ... < e_n = 1; returns #{k in 1..n-1 : |cos| >= e_k}.
 __device__ __forceinline__ int bin_abscos(const double x[4][4], const double w[4], double W,
                                           const double P[4], double M2, double eM, double kdot,
@@ -241,23 +254,24 @@ __device__ __forceinline__ int bin_abscos(const double x[4][4], const double w[4
     const double D = A * B;
     const double eD = fma(A + eA, eB, fma(B, eA, U64 * D));
     ok = ok && (eD <= 0.25 * D);
-    const double r = 1.0 / sqrt(D);
+    double rel;
+    const double r = rsqrt_cert(D, rel, ok);
     const double v = dabs(Nn) * r;
-    const double eps = fma(1.001, fma(eNn, r, eD * r * r), 11.0 * U64);
+    const double eps = ratio_eps(v, r, rel, eNn, eD);
+    const double vhi = v + eps, vlo = v - eps;
     int bin = 0;
     for (int k = 1; k < n; ++k) {
         const double e = edges[k];
-        const bool ge = (v - eps) >= e;
-        const bool lt = (v + eps) < e;
+        const bool ge = vlo >= e;
         bin += ge ? 1 : 0;
-        ok = ok && (ge || lt);
+        ok = ok && (ge || vhi < e);
     }
     sure = sure && ok;
     return bin;
 }
 
-// Invariant mass of the kernel slots in ``mask``.  ed: [sq_lo(n+1) | sq_hi(n+1)].
-// Returns the bin or -1 (out of range).
+// Invariant mass of the kernel slots in ``mask``.  ed: [sq_lo(n+1) | sq_hi(n+1)]
+// with sq_lo_k <= e_k^2 <= sq_hi_k.  Returns the bin or -1 (out of range).
 __device__ __forceinline__ int bin_mass(const double x[4][4], const double w[4], int mask,
                                         const double *ed, int n, double glo, double ginv, bool &sure)
 {
@@ -274,12 +288,13 @@ __device__ __forceinline__ int bin_mass(const double x[4][4], const double w[4],
     const double em = (12.4 * U64) * WS * WS;
     const double *sqlo = ed, *sqhi = ed + (n + 1);
     const double mlo = m2 - em, mhi = m2 + em;
-    // guess from a uniform grid, then certify against the two neighbouring edges
+    // guess on a uniform grid in m, then certify against the two neighbouring edges
     const float mg = sqrtf(fmaxf((float)m2, 0.0f));
-    int j = (int)floorf((float)(((double)mg - glo) * ginv));
-    j = j < 0 ? 0 : (j > n - 1 ? n - 1 : j);
-    bool ok = mlo >= sqhi[j] && (j == n - 1 ? mhi <= sqlo[n] : mhi < sqlo[j + 1]);
-    if (ok) return j;
+    const float t = (float)(((double)mg - glo) * ginv);
+    int j = 0;
+    if (t >= (float)(n - 1)) j = n - 1;
+    else if (t >= 0.0f) j = (int)t;
+    if (mlo >= sqhi[j] && (j == n - 1 ? mhi <= sqlo[n] : mhi < sqlo[j + 1])) return j;
     // full scan
     if (mhi < sqlo[0] || mlo > sqhi[n]) return -1;          // certainly outside
     if (!(mlo >= sqhi[0] && mhi <= sqlo[n])) {               // not certainly inside
@@ -290,9 +305,8 @@ __device__ __forceinline__ int bin_mass(const double x[4][4], const double w[4],
     bool dec = true;
     for (int k = 1; k < n; ++k) {
         const bool ge = mlo >= sqhi[k];
-        const bool lt = mhi < sqlo[k];
         bin += ge ? 1 : 0;
-        dec = dec && (ge || lt);
+        dec = dec && (ge || mhi < sqlo[k]);
     }
     sure = sure && dec;
     return bin;
@@ -313,6 +327,7 @@ __device__ __forceinline__ EvOut eval_event(const Tin (&q)[4][4], int tag, const
     o.cls = CLS_DEFER;
     o.bin = -1;
     o.t2 = 0;
+    o.why = 1;
     o.ct = 0.0;
     if (tag != 0 && tag != 1) {
         o.cls = CLS_INVALID;
@@ -357,6 +372,7 @@ __device__ __forceinline__ EvOut eval_event(const Tin (&q)[4][4], int tag, const
     }
     const double ct = g.sigma > 0 ? det : -det;
     o.ct = ct;
+    o.why = 2;
     if (!sure) return o;
     const int cls = tag == 0 ? (ct > 0.0 ? CLS_I : CLS_II) : (ct < 0.0 ? CLS_III : CLS_IV);
 
@@ -365,13 +381,15 @@ __device__ __forceinline__ EvOut eval_event(const Tin (&q)[4][4], int tag, const
     bool oor = false;
     bool bsure = true;
     for (int a = 0; a < g.naxes; ++a) {
+        if (bsure) o.why = 3 + a;
         const int kind = a == 0 ? g.kind0 : g.kind1;
         const int nb = a == 0 ? g.nb0 : g.nb1;
         const int sl = a == 0 ? g.slots0 : g.slots1;
         const double *ed = a == 0 ? g.e0 : g.e1;
         int j;
         if (kind == AX_ABSPHI) {
-            j = bin_absphi(x, w, W, M2, eM, KDOT, ed, nb, bsure);
+            const double wmax = dmax(dmax(w[0], w[1]), dmax(w[2], w[3]));
+            j = bin_absphi(x, W, wmax, M2, KDOT, ed, nb, bsure);
         } else if (kind == AX_MASS) {
             j = bin_mass(x, w, sl, ed, nb, a == 0 ? g.glo0 : g.glo1, a == 0 ? g.ginv0 : g.ginv1, bsure);
         } else {
@@ -391,16 +409,74 @@ __device__ __forceinline__ uint32_t wave_count(bool p)
     return (uint32_t)__popcll(__ballot(p));
 }
 
-template <typename Tin>
-__device__ __forceinline__ Tin ld(const void *p, int64_t i)
+template <typename T>
+__device__ __forceinline__ T ldnt(const void *p, int64_t i)
 {
-    return __builtin_nontemporal_load(reinterpret_cast<const Tin *>(p) + i);
+    return __builtin_nontemporal_load(reinterpret_cast<const T *>(p) + i);
 }
 
-template <typename Tin, int PREC, int MODE>
+// Load EPL consecutive events (EPL = 1, 2 or 4 per lane) starting at ``base``
+// (a multiple of EPL) from the 16 component arrays and the tag array.
+template <typename Tin, int EPL>
+__device__ __forceinline__ void load_events(const void *const (&ptr)[16], const int8_t *tag, int64_t base,
+                                            bool vec_ok, int64_t n_valid, Tin (&q)[EPL][4][4], int (&tg)[EPL])
+{
+    constexpr int BYTES = EPL * (int)sizeof(Tin);
+    if (EPL > 1 && !(vec_ok && base + EPL <= n_valid)) {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+            const int64_t i = base + e;
+            const bool in = i < n_valid;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) q[e][k >> 2][k & 3] = in ? ldnt<Tin>(ptr[k], i) : (Tin)0;
+            tg[e] = in ? (int)tag[i] : -1;
+        }
+        return;
+    }
+    if constexpr (EPL == 1) {
+        const bool in = base < n_valid;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) q[0][k >> 2][k & 3] = in ? ldnt<Tin>(ptr[k], base) : (Tin)0;
+        tg[0] = in ? (int)tag[base] : -1;
+    } else if constexpr (BYTES == 8) {
+        typedef Tin v2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const v2 v = ldnt<v2>(ptr[k], base >> 1);
+            q[0][k >> 2][k & 3] = v.x;
+            q[1][k >> 2][k & 3] = v.y;
+        }
+        const uint16_t t = ldnt<uint16_t>(tag, base >> 1);
+        tg[0] = (int)(int8_t)(t & 0xff);
+        tg[1] = (int)(int8_t)(t >> 8);
+    } else if constexpr (EPL == 4 && sizeof(Tin) == 4) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const f32x4 v = ldnt<f32x4>(ptr[k], base >> 2);
+            q[0][k >> 2][k & 3] = v.x;
+            q[1][k >> 2][k & 3] = v.y;
+            q[2][k >> 2][k & 3] = v.z;
+            q[3][k >> 2][k & 3] = v.w;
+        }
+        const uint32_t t = ldnt<uint32_t>(tag, base >> 2);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) tg[e] = (int)(int8_t)(t >> (8 * e));
+    } else {   // EPL == 2, double: 16-byte loads
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const f64x2 v = ldnt<f64x2>(ptr[k], base >> 1);
+            q[0][k >> 2][k & 3] = v.x;
+            q[1][k >> 2][k & 3] = v.y;
+        }
+        const uint16_t t = ldnt<uint16_t>(tag, base >> 1);
+        tg[0] = (int)(int8_t)(t & 0xff);
+        tg[1] = (int)(int8_t)(t >> 8);
+    }
+}
+
+template <typename Tin, int PREC, int MODE, int EPL>
 __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
 {
-    constexpr int EPL = sizeof(Tin) == 4 ? 4 : 2;   // events per lane per step (16-byte loads)
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t *hist = reinterpret_cast<uint32_t *>(smem);
     const int hist_words = kp.lds_copies * kp.hist_stride;
@@ -426,11 +502,22 @@ __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
         const int64_t sv1 = s + 1 < kp.nsamples ? kp.samples[s + 1].vstart : kp.vtotal;
         if (sv1 <= vbeg) continue;
         const int64_t segend = vend < sv1 ? vend : sv1;
+        const int64_t n = S->n;
         const int64_t ev0 = vbeg - sv0;
-        const int64_t ev1 = (segend - sv0) < S->n ? (segend - sv0) : S->n;
+        const int64_t ev1 = (segend - sv0) < n ? (segend - sv0) : n;
         vbeg = segend;
         if (ev1 <= ev0) continue;
 
+        // everything the event loop needs, read once per segment
+        const void *ptr[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) ptr[k] = S->p[k];
+        const int8_t *tagp = S->tag;
+        const bool vec = S->vec != 0;
+        uint64_t *counts = S->counts;
+        uint64_t *stats = S->stats;
+        int8_t *cls_out = S->cls_out;
+        double *ct_out = S->ct_out;
         Seg g;
         g.sigma = S->sigma;
         g.naxes = MODE == 0 ? S->naxes : 0;
@@ -446,60 +533,23 @@ __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
         g.ginv1 = S->guess_inv[1];
         const int nd0 = g.naxes > 0 ? edge_doubles(g.kind0, g.nb0) : 0;
         const int nd1 = g.naxes > 1 ? edge_doubles(g.kind1, g.nb1) : 0;
+        const int eoff0 = S->eoff[0], eoff1 = S->eoff[1];
+        const int nrow = (S->nbtot + 1) * 4;
         g.e0 = ecache;
         g.e1 = ecache + nd0;
-        const int nrow = (S->nbtot + 1) * 4;
         const int ncnt = nrow + NSTAT;
         for (int i = tid; i < hist_words; i += nthr) hist[i] = 0;
-        for (int i = tid; i < nd0; i += nthr) ecache[i] = kp.edges[S->eoff[0] + i];
-        for (int i = tid; i < nd1; i += nthr) ecache[nd0 + i] = kp.edges[S->eoff[1] + i];
+        for (int i = tid; i < nd0; i += nthr) ecache[i] = kp.edges[eoff0 + i];
+        for (int i = tid; i < nd1; i += nthr) ecache[nd0 + i] = kp.edges[eoff1 + i];
         __syncthreads();
 
         uint32_t wc0 = 0, wc1 = 0, wc2 = 0, wc3 = 0, wzero = 0, winv = 0, woor = 0, wt2 = 0,
                  wt3 = 0, wun = 0;
-        const bool vec = S->vec != 0;
         for (int64_t t0 = ev0; t0 < ev1; t0 += (int64_t)EPL * nthr) {
             const int64_t base = t0 + (int64_t)EPL * tid;
             Tin q[EPL][4][4];
             int tg[EPL];
-            if (vec && base + EPL <= S->n) {
-#pragma unroll
-                for (int k = 0; k < 16; ++k) {
-                    if constexpr (EPL == 4) {
-                        const f32x4 v = __builtin_nontemporal_load(
-                            reinterpret_cast<const f32x4 *>(S->p[k]) + (base >> 2));
-                        q[0][k >> 2][k & 3] = v.x;
-                        q[1][k >> 2][k & 3] = v.y;
-                        q[2][k >> 2][k & 3] = v.z;
-                        q[3][k >> 2][k & 3] = v.w;
-                    } else {
-                        const f64x2 v = __builtin_nontemporal_load(
-                            reinterpret_cast<const f64x2 *>(S->p[k]) + (base >> 1));
-                        q[0][k >> 2][k & 3] = v.x;
-                        q[1][k >> 2][k & 3] = v.y;
-                    }
-                }
-                if constexpr (EPL == 4) {
-                    const uint32_t t = __builtin_nontemporal_load(
-                        reinterpret_cast<const uint32_t *>(S->tag) + (base >> 2));
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) tg[e] = (int)(int8_t)(t >> (8 * e));
-                } else {
-                    const uint16_t t = __builtin_nontemporal_load(
-                        reinterpret_cast<const uint16_t *>(S->tag) + (base >> 1));
-                    tg[0] = (int)(int8_t)(t & 0xff);
-                    tg[1] = (int)(int8_t)(t >> 8);
-                }
-            } else {
-#pragma unroll
-                for (int e = 0; e < EPL; ++e) {
-                    const int64_t i = base + e;
-                    const bool in = i < ev1;
-#pragma unroll
-                    for (int k = 0; k < 16; ++k) q[e][k >> 2][k & 3] = in ? ld<Tin>(S->p[k], i) : (Tin)0;
-                    tg[e] = in ? (int)S->tag[i] : -1;
-                }
-            }
+            load_events<Tin, EPL>(ptr, tagp, base, vec, ev1, q, tg);
 #pragma unroll
             for (int e = 0; e < EPL; ++e) {
                 const int64_t i = base + e;
@@ -511,34 +561,42 @@ __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
                     o.cls = -1;
                     o.bin = -1;
                     o.t2 = 0;
+                    o.why = 0;
                     o.ct = 0.0;
                 }
                 bool listed = false, unres = false;
                 if (o.cls == CLS_DEFER) {
                     const uint32_t slot = atomicAdd(kp.xcount, 1u);
                     if (slot < kp.xcap) {
-                        kp.xlist[slot] = ((uint64_t)s << 40) | (uint64_t)i;
+                        kp.xlist[slot] = ((uint64_t)o.why << 60) | ((uint64_t)s << 40) | (uint64_t)i;
                         listed = true;
                     } else {
                         unres = true;
                     }
                 }
                 if (MODE == 1 && in) {
-                    S->cls_out[i] = (int8_t)(unres ? CLS_UNRESOLVED : (o.cls == CLS_DEFER ? CLS_DEFER : o.cls));
-                    if (S->ct_out) S->ct_out[i] = o.ct;
+                    cls_out[i] = (int8_t)(unres ? CLS_UNRESOLVED : o.cls);
+                    if (ct_out) ct_out[i] = o.ct;
                 }
                 if (MODE == 0 && o.cls >= 0 && o.cls < 4 && o.bin >= 0 && g.naxes > 0)
                     atomicAdd(&myhist[(1 + o.bin) * 4 + o.cls], 1u);
-                wc0 += wave_count(o.cls == CLS_I);
-                wc1 += wave_count(o.cls == CLS_II);
-                wc2 += wave_count(o.cls == CLS_III);
-                wc3 += wave_count(o.cls == CLS_IV);
-                wzero += wave_count(o.cls == CLS_ZERO);
-                winv += wave_count(o.cls == CLS_INVALID);
-                woor += wave_count(o.cls >= 0 && o.cls < 4 && o.bin < 0 && g.naxes > 0);
-                wt2 += wave_count(o.t2 != 0);
-                wt3 += wave_count(listed);
-                wun += wave_count(unres);
+                if (MODE == 0) {
+                    wc0 += wave_count(o.cls == CLS_I);
+                    wc1 += wave_count(o.cls == CLS_II);
+                    wc2 += wave_count(o.cls == CLS_III);
+                    wc3 += wave_count(o.cls == CLS_IV);
+                }
+                // rare outcomes: one ballot decides whether the wave counts them
+                const bool rare = (o.cls >= CLS_ZERO) || o.t2 || (o.cls >= 0 && o.cls < 4 && o.bin < 0 &&
+                                                                 g.naxes > 0);
+                if (__ballot(rare)) {
+                    wzero += wave_count(o.cls == CLS_ZERO);
+                    winv += wave_count(o.cls == CLS_INVALID);
+                    woor += wave_count(o.cls >= 0 && o.cls < 4 && o.bin < 0 && g.naxes > 0);
+                    wt2 += wave_count(o.t2 != 0);
+                    wt3 += wave_count(listed);
+                    wun += wave_count(unres);
+                }
             }
         }
         if (lane == 0) {
@@ -560,11 +618,11 @@ __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
             uint32_t v = 0;
             for (int k = 0; k < kp.lds_copies; ++k) v += hist[k * kp.hist_stride + i];
             if (i < nrow) {
-                if (v && S->counts) atomicAdd((unsigned long long *)(S->counts + i), (unsigned long long)v);
+                if (v && counts) atomicAdd((unsigned long long *)(counts + i), (unsigned long long)v);
             } else if (i - nrow == ST_EVENTS) {
-                atomicAdd((unsigned long long *)(S->stats + ST_EVENTS), (unsigned long long)(ev1 - ev0));
+                atomicAdd((unsigned long long *)(stats + ST_EVENTS), (unsigned long long)(ev1 - ev0));
             } else if (v) {
-                atomicAdd((unsigned long long *)(S->stats + (i - nrow)), (unsigned long long)v);
+                atomicAdd((unsigned long long *)(stats + (i - nrow)), (unsigned long long)v);
             }
         }
         __syncthreads();
@@ -574,23 +632,36 @@ __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
-hipError_t launch_pass(int dtype, int prec, int mode, const KParams &kp, int grid, int block,
+namespace {
+template <typename T, int P, int M>
+void launch_epl(int epl, const KParams &kp, int grid, int block, size_t lds, hipStream_t st)
+{
+    if constexpr (sizeof(T) == 4) {
+        if (epl >= 4) {
+            hipLaunchKernelGGL((tp_pass_kernel<T, P, M, 4>), dim3(grid), dim3(block), lds, st, kp);
+            return;
+        }
+    }
+    if (epl >= 2) hipLaunchKernelGGL((tp_pass_kernel<T, P, M, 2>), dim3(grid), dim3(block), lds, st, kp);
+    else hipLaunchKernelGGL((tp_pass_kernel<T, P, M, 1>), dim3(grid), dim3(block), lds, st, kp);
+}
+}  // namespace
+
+hipError_t launch_pass(int dtype, int prec, int mode, int epl, const KParams &kp, int grid, int block,
                        size_t lds, hipStream_t st)
 {
-#define TP_L(T, P, M) hipLaunchKernelGGL((tp_pass_kernel<T, P, M>), dim3(grid), dim3(block), lds, st, kp)
     if (dtype == 0) {
         if (prec == 1) {
-            if (mode == 0) TP_L(float, 1, 0);
-            else TP_L(float, 1, 1);
+            if (mode == 0) launch_epl<float, 1, 0>(epl, kp, grid, block, lds, st);
+            else launch_epl<float, 1, 1>(epl, kp, grid, block, lds, st);
         } else {
-            if (mode == 0) TP_L(float, 0, 0);
-            else TP_L(float, 0, 1);
+            if (mode == 0) launch_epl<float, 0, 0>(epl, kp, grid, block, lds, st);
+            else launch_epl<float, 0, 1>(epl, kp, grid, block, lds, st);
         }
     } else {
-        if (mode == 0) TP_L(double, 0, 0);
-        else TP_L(double, 0, 1);
+        if (mode == 0) launch_epl<double, 0, 0>(epl, kp, grid, block, lds, st);
+        else launch_epl<double, 0, 1>(epl, kp, grid, block, lds, st);
     }
-#undef TP_L
     return hipGetLastError();
 }
 

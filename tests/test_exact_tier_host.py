@@ -20,7 +20,7 @@ OUT = os.path.join(ROOT, "tests", "_build", "libexact_harness.so")
 @pytest.fixture(scope="module")
 def hx():
     os.makedirs(os.path.dirname(OUT), exist_ok=True)
-    subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-I",
+    subprocess.run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-shared", "-fPIC", "-I",
                     os.path.join(ROOT, "paper_1612_04705_amd", "csrc"), SRC, "-o", OUT], check=True)
     lib = ctypes.CDLL(OUT)
     lib.hx_decide.restype = ctypes.c_int
@@ -36,8 +36,10 @@ def perm_sign(p):
     return s
 
 
-def decide(hx, comps_slot, tag, triple, planes, axes, is_f32):
-    """Call the harness with the kernel-order layout (kernel slot t = channel slot planes[t])."""
+def decide(hx, comps_slot, tag, triple, planes, axes, is_f32, dw=False):
+    """Call the harness with the kernel-order layout (kernel slot t = channel slot planes[t]).
+
+    dw: use the double-word tier (returns class 7 when it does not decide)."""
     inv = [0] * 4
     for t, s in enumerate(planes):
         inv[s] = t
@@ -63,19 +65,33 @@ def decide(hx, comps_slot, tag, triple, planes, axes, is_f32):
     while len(eds) < 2:
         eds.append(None)
     b = ctypes.c_int()
-    c = hx.hx_decide((ctypes.c_double * 16)(*k), int(is_f32), int(tag), sigma, len(axes), kinds, nb, sl,
-                     eds[0], eds[1], ctypes.byref(b))
+    if dw:
+        c = hx.hx_decide_dw((ctypes.c_double * 16)(*k), int(tag), sigma, len(axes), kinds, nb, sl,
+                            eds[0], eds[1], ctypes.byref(b))
+    else:
+        c = hx.hx_decide((ctypes.c_double * 16)(*k), int(is_f32), int(tag), sigma, len(axes), kinds, nb, sl,
+                         eds[0], eds[1], ctypes.byref(b))
     return c, (b.value if axes and c < 4 else None)
 
 
 def _check(hx, comps, tag, triple, planes, axes, is_f32, idx):
+    """Both the exact integer tier and (where it decides) the double-word tier
+    agree with the oracle's Fractions; returns how many the double-word tier left."""
     ax = [(a.kind, a.slots, list(map(float, a.edges))) for a in axes]
+    undecided = 0
     for i in idx:
         ev = [[float(comps[s, c, i]) for c in range(4)] for s in range(4)]
         want = exact.exact_decision(ev, int(tag[i]), triple, planes, ax)
         got = decide(hx, ev, int(tag[i]), triple, planes, ax, is_f32)
         want = (want[0], want[1] if want[0] < 4 else None)
         assert got == want, (i, got, want)
+        if all(np.isfinite(v) for row in ev for v in row):
+            gdw = decide(hx, ev, int(tag[i]), triple, planes, ax, is_f32, dw=True)
+            if gdw[0] == 7:
+                undecided += 1
+            else:
+                assert gdw == want, ("double-word", i, gdw, want)
+    return undecided
 
 
 @pytest.mark.parametrize("chname,axes_fn,dtype", [
@@ -89,7 +105,18 @@ def test_exact_tier_random_events(hx, chname, axes_fn, dtype):
     ch = synth.CHANNELS[chname]
     s = synth.generate(ch, 150, 31, dtype=dtype)
     comps, tag = s.numpy()
-    _check(hx, comps, tag, ch.triple, ch.planes, axes_fn(ch), dtype == torch.float32, range(150))
+    left = _check(hx, comps, tag, ch.triple, ch.planes, axes_fn(ch), dtype == torch.float32, range(150))
+    assert left == 0        # random events never need the integer tier
+
+
+@pytest.mark.parametrize("gamma", [1e3, 1e5])
+def test_double_word_tier_extreme_boost(hx, gamma):
+    ch = synth.CHANNELS["Lb_pKpipi"]
+    s = synth.generate(ch, 60, 34, fixed_gamma=gamma)
+    comps, tag = s.numpy()
+    left = _check(hx, comps, tag, ch.triple, ch.planes, [synth.absphi_axis(10), synth.lb_mass03_axis(ch)],
+                  True, range(60))
+    assert left <= 3
 
 
 def test_exact_tier_handbuilt(hx):
