@@ -53,10 +53,10 @@ def traffic_from_profiles(workload):
     return e.get("hbm_bytes_per_launch")
 
 
-def make_workload(config, device, scale):
+def make_workload(name, device, scale):
     import torch
     from paper_1612_04705_amd import synth, tpasym
-    specs = synth.config_specs(config, scale)
+    specs = synth.workload_specs(name, scale)
     items, samples = [], []
     t0 = time.time()
     for spec in specs:
@@ -110,13 +110,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=4)
+    ap.add_argument("--workload", default="lb_batch64_1e3to1e7",
+                    help="named workload (paper_1612_04705_amd.synth.WORKLOADS)")
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-events", type=float, default=6e6)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tuning", default=None,
+                    help="fixed launch shape block,wg_per_cu,lds_copies,events_per_lane (skips the autotuner)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -132,7 +137,7 @@ def main():
     torch.cuda.set_device(dev)
     tpasym.load()
     prec = tpasym.TP_PREC_F32_RECHECK if args.precision == "f32" else tpasym.TP_PREC_F64
-    specs, samples, items = make_workload(args.config, dev, args.scale)
+    specs, samples, items = make_workload(args.workload, dev, args.scale)
     nevents = sum(s.n for _, s in samples)
     f64_store = samples[0][1].comps[0][0].dtype == torch.float64
     bpe = BYTES_F64 if f64_store else BYTES_F32
@@ -140,7 +145,9 @@ def main():
     stream = torch.cuda.current_stream()
 
     tuning = None
-    if not args.no_autotune:
+    if args.tuning:
+        tuning = tpasym.Tuning(*[int(v) for v in args.tuning.split(",")])
+    elif not args.no_autotune:
         t0 = time.time()
         tuning = batch.autotune(prec)
         log(f"autotune: {tuning.as_dict()} in {time.time() - t0:.1f}s")
@@ -164,6 +171,15 @@ def main():
     ms_per_step = total_ms / args.steps
     value = nevents / (ms_per_step / 1e3)
     log(f"{args.steps} steps: {ms_per_step:.4f} ms/step, kernel {kern_ms:.4f} ms over {launches} launches")
+
+    if args.copy_calib:
+        # an elementwise kernel (not a DMA copy): reads 1 GiB, writes 1 GiB
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     # statistics and parity-relevant totals (counts accumulate over warmup + steps)
     reps = args.warmup + args.steps
@@ -190,9 +206,7 @@ def main():
                                b[3].cpu().numpy().view(np.uint64) // (f64_steps + 1))
                 for a, b in zip(items, f64_items))
 
-    wl = {1: "config1_Lb_ppipipi_f64_1e5", 2: "config2_Lb_ppipipi_1e7_12phi",
-          3: "config3_Lb_pKpipi_1e8_10phix8m", 4: "config4_batched_64_samples",
-          5: "config5_D0_KKpipi_5e8_32x32m"}[args.config]
+    wl = args.workload
     if args.scale != 1.0:
         wl += f"_scale{args.scale:g}"
     achieved = nevents * bpe / (kern_ms / 1e3) / 1e9 if kern_ms > 0 else None

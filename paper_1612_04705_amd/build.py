@@ -31,31 +31,35 @@ def _hipcc():
     return os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
-def _compile(src, extra, verbose):
-    obj = os.path.join(OBJ, src + ".o")
+def _compile(name, path, extra, verbose):
+    obj = os.path.join(OBJ, os.path.basename(path) + ".o")
     cmd = [_hipcc(), *FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
-           os.path.join(CSRC, src), "-o", obj]
+           path, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}{r.stderr}")
+        raise RuntimeError(f"hipcc failed on {path}:\n{r.stdout}{r.stderr}")
     return obj, r.stderr
 
 
-def build(verbose: bool = False, extra=()) -> str:
+def build(verbose: bool = False, extra=(), sources=None, out=None) -> str:
+    """Compile every source (or ``sources``: {name: path}) and link ``out`` (default libtpasym.so)."""
     os.makedirs(OBJ, exist_ok=True)
-    with ThreadPoolExecutor(len(SOURCES)) as ex:
-        res = list(ex.map(lambda s: _compile(s, list(extra), verbose), SOURCES))
+    srcs = {s: os.path.join(CSRC, s) for s in SOURCES}
+    srcs.update(sources or {})
+    with ThreadPoolExecutor(len(srcs)) as ex:
+        res = list(ex.map(lambda kv: _compile(kv[0], kv[1], list(extra), verbose), srcs.items()))
     for _, err in res:
         if verbose and err.strip():
             sys.stderr.write(err)
-    cmd = [_hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *[o for o, _ in res], "-o", LIB + ".tmp"]
+    lib = out or LIB
+    cmd = [_hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *[o for o, _ in res], "-o", lib + ".tmp"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -280,6 +280,7 @@ void fill_sample(KSample &k, const tp_events &ev, const tp_channel &ch, const tp
     int dabc[4] = { D, ch.triple[0], ch.triple[1], ch.triple[2] };
     k.sigma = perm_sign(dabc, 4) * perm_sign(ch.planes, 4);
     k.naxes = bn ? bn->naxes : 0;
+    k.kind[0] = k.kind[1] = AX_NONE;
     k.nbtot = 0;
     if (bn && bn->naxes > 0) {
         k.nbtot = 1;

@@ -8,7 +8,7 @@ namespace tpk {
 enum { MAXBINS = 1024, NSTAT = 8 };
 enum { CLS_I = 0, CLS_II = 1, CLS_III = 2, CLS_IV = 3, CLS_ZERO = 4, CLS_INVALID = 5,
        CLS_UNRESOLVED = 6, CLS_DEFER = 7 };
-enum { AX_ABSPHI = 0, AX_MASS = 1, AX_ABSCOS = 2 };
+enum { AX_ABSPHI = 0, AX_MASS = 1, AX_ABSCOS = 2, AX_NONE = 3 };
 // stats slots (same order as tp_stats)
 enum { ST_EVENTS = 0, ST_ZERO = 1, ST_INVALID = 2, ST_OOR = 3, ST_TIER2 = 4, ST_TIER3 = 5,
        ST_UNRESOLVED = 6 };

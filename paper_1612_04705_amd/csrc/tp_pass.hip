@@ -313,16 +313,29 @@ __device__ __forceinline__ int bin_mass(const double x[4][4], const double w[4],
 }
 
 struct Seg {
-    int32_t sigma, naxes, kind0, kind1, nb0, nb1, slots0, slots1;
+    int32_t sigma, nb0, nb1, slots0, slots1;
     double glo0, ginv0, glo1, ginv1;
     const double *e0, *e1;    // LDS edge data of each axis
 };
 
-template <typename Tin, int PREC>
+// One axis of compile-time kind KIND: bin index, or -1 (out of range).
+template <int KIND, bool EXACTP>
+__device__ __forceinline__ int axis_bin(const double (&x)[4][4], const double (&w)[4], double W, double wmax,
+                                        const double (&P)[4], double M2, double eM, int nb, int sl,
+                                        const double *ed, double glo, double ginv, bool &sure)
+{
+    constexpr double KDOT = EXACTP ? 3.02 : 4.02;
+    if constexpr (KIND == AX_ABSPHI) return bin_absphi(x, W, wmax, M2, KDOT, ed, nb, sure);
+    else if constexpr (KIND == AX_MASS) return bin_mass(x, w, sl, ed, nb, glo, ginv, sure);
+    else return bin_abscos(x, w, W, P, M2, eM, KDOT, sl, ed, nb, sure);
+}
+
+// Whole event, with the binning scheme (K0, K1; AX_NONE = absent) fixed at
+// compile time.
+template <typename Tin, int PREC, int K0, int K1>
 __device__ __forceinline__ EvOut eval_event(const Tin (&q)[4][4], int tag, const Seg &g)
 {
     constexpr bool EXACTP = sizeof(Tin) == 4;
-    constexpr double KDOT = EXACTP ? 3.02 : 4.02;
     EvOut o;
     o.cls = CLS_DEFER;
     o.bin = -1;
@@ -347,14 +360,13 @@ __device__ __forceinline__ EvOut eval_event(const Tin (&q)[4][4], int tag, const
 #pragma unroll
     for (int c = 0; c < 4; ++c) P[c] = (x[0][c] + x[1][c]) + (x[2][c] + x[3][c]);
     const double M2 = fma(-P[3], P[3], fma(-P[2], P[2], fma(-P[1], P[1], P[0] * P[0])));
-    const double eM = (10.2 * U64) * W * W;
     const double Emin = fmin(fmin(x[0][0], x[1][0]), fmin(x[2][0], x[3][0]));
     if (!(Emin >= 0.0 && P[0] > 0.0 && M2 > (11.0 * U64) * W * W)) return o;
 
     // sign of the triple product
     double det;
     bool sure;
-    if (PREC == 1) {
+    if constexpr (PREC == 1) {
         float det32;
         float qf[4][4];
 #pragma unroll
@@ -375,33 +387,31 @@ __device__ __forceinline__ EvOut eval_event(const Tin (&q)[4][4], int tag, const
     o.why = 2;
     if (!sure) return o;
     const int cls = tag == 0 ? (ct > 0.0 ? CLS_I : CLS_II) : (ct < 0.0 ? CLS_III : CLS_IV);
-
-    // bins
-    int bin = 0;
-    bool oor = false;
-    bool bsure = true;
-    for (int a = 0; a < g.naxes; ++a) {
-        if (bsure) o.why = 3 + a;
-        const int kind = a == 0 ? g.kind0 : g.kind1;
-        const int nb = a == 0 ? g.nb0 : g.nb1;
-        const int sl = a == 0 ? g.slots0 : g.slots1;
-        const double *ed = a == 0 ? g.e0 : g.e1;
-        int j;
-        if (kind == AX_ABSPHI) {
-            const double wmax = dmax(dmax(w[0], w[1]), dmax(w[2], w[3]));
-            j = bin_absphi(x, W, wmax, M2, KDOT, ed, nb, bsure);
-        } else if (kind == AX_MASS) {
-            j = bin_mass(x, w, sl, ed, nb, a == 0 ? g.glo0 : g.glo1, a == 0 ? g.ginv0 : g.ginv1, bsure);
-        } else {
-            j = bin_abscos(x, w, W, P, M2, eM, KDOT, sl, ed, nb, bsure);
+    if constexpr (K0 == AX_NONE) {
+        o.cls = cls;
+        o.bin = 0;
+        return o;
+    } else {
+        const double eM = (10.2 * U64) * W * W;
+        double wmax = 0.0;
+        if constexpr (K0 == AX_ABSPHI || K1 == AX_ABSPHI) wmax = dmax(dmax(w[0], w[1]), dmax(w[2], w[3]));
+        bool bsure = true;
+        o.why = 3;
+        const int j0 = axis_bin<K0, EXACTP>(x, w, W, wmax, P, M2, eM, g.nb0, g.slots0, g.e0, g.glo0, g.ginv0, bsure);
+        bool oor = j0 < 0;
+        int bin = j0 < 0 ? 0 : j0;
+        if constexpr (K1 != AX_NONE) {
+            if (bsure) o.why = 4;
+            const int j1 = axis_bin<K1, EXACTP>(x, w, W, wmax, P, M2, eM, g.nb1, g.slots1, g.e1, g.glo1,
+                                                g.ginv1, bsure);
+            oor = oor || j1 < 0;
+            bin = bin * g.nb1 + (j1 < 0 ? 0 : j1);
         }
-        if (j < 0) oor = true;
-        bin = bin * nb + (j < 0 ? 0 : j);
+        if (!bsure) return o;
+        o.cls = cls;
+        o.bin = oor ? -1 : bin;
+        return o;
     }
-    if (!bsure) return o;
-    o.cls = cls;
-    o.bin = oor ? -1 : bin;
-    return o;
 }
 
 __device__ __forceinline__ uint32_t wave_count(bool p)
@@ -412,7 +422,8 @@ __device__ __forceinline__ uint32_t wave_count(bool p)
 template <typename T>
 __device__ __forceinline__ T ldnt(const void *p, int64_t i)
 {
-    return __builtin_nontemporal_load(reinterpret_cast<const T *>(p) + i);
+    typedef const T __attribute__((address_space(1))) *gptr;
+    return __builtin_nontemporal_load((gptr)p + i);
 }
 
 // Load EPL consecutive events (EPL = 1, 2 or 4 per lane) starting at ``base``
@@ -429,7 +440,7 @@ __device__ __forceinline__ void load_events(const void *const (&ptr)[16], const 
             const bool in = i < n_valid;
 #pragma unroll
             for (int k = 0; k < 16; ++k) q[e][k >> 2][k & 3] = in ? ldnt<Tin>(ptr[k], i) : (Tin)0;
-            tg[e] = in ? (int)tag[i] : -1;
+            tg[e] = in ? (int)ldnt<int8_t>(tag, i) : -1;
         }
         return;
     }
@@ -437,7 +448,7 @@ __device__ __forceinline__ void load_events(const void *const (&ptr)[16], const 
         const bool in = base < n_valid;
 #pragma unroll
         for (int k = 0; k < 16; ++k) q[0][k >> 2][k & 3] = in ? ldnt<Tin>(ptr[k], base) : (Tin)0;
-        tg[0] = in ? (int)tag[base] : -1;
+        tg[0] = in ? (int)ldnt<int8_t>(tag, base) : -1;
     } else if constexpr (BYTES == 8) {
         typedef Tin v2 __attribute__((ext_vector_type(2)));
 #pragma unroll
@@ -471,6 +482,100 @@ __device__ __forceinline__ void load_events(const void *const (&ptr)[16], const 
         const uint16_t t = ldnt<uint16_t>(tag, base >> 1);
         tg[0] = (int)(int8_t)(t & 0xff);
         tg[1] = (int)(int8_t)(t >> 8);
+    }
+}
+
+struct WaveCounts {
+    uint32_t c0, c1, c2, c3, zero, inv, oor, t2, t3, un;
+};
+
+struct SegIO {
+    const void *ptr[16];
+    const int8_t *tag;
+    int8_t *cls_out;
+    double *ct_out;
+    bool vec;
+};
+
+// The event loop of one segment (events [ev0, ev1) of sample s) for one
+// binning scheme.
+template <typename Tin, int PREC, int MODE, int EPL, int K0, int K1>
+__device__ __forceinline__ void run_segment(const KParams &kp, int s, const SegIO &io, const Seg &g,
+                                            int64_t ev0, int64_t ev1, uint32_t *myhist, WaveCounts &wc)
+{
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    constexpr bool BINNED = MODE == 0 && K0 != AX_NONE;
+    // Register double buffer: the next tile's inputs are requested before the
+    // current tile is evaluated, so every wave keeps loads in flight.
+    constexpr bool PF = EPL <= 2;
+    const int64_t step = (int64_t)EPL * nthr;
+    Tin qn[EPL][4][4];
+    int tgn[EPL];
+    if (PF && ev0 < ev1) load_events<Tin, EPL>(io.ptr, io.tag, ev0 + (int64_t)EPL * tid, io.vec, ev1, qn, tgn);
+    for (int64_t t0 = ev0; t0 < ev1; t0 += step) {
+        const int64_t base = t0 + (int64_t)EPL * tid;
+        Tin q[EPL][4][4];
+        int tg[EPL];
+        if constexpr (PF) {
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) {
+                tg[e] = tgn[e];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) q[e][k >> 2][k & 3] = qn[e][k >> 2][k & 3];
+            }
+            if (t0 + step < ev1) load_events<Tin, EPL>(io.ptr, io.tag, base + step, io.vec, ev1, qn, tgn);
+        } else {
+            load_events<Tin, EPL>(io.ptr, io.tag, base, io.vec, ev1, q, tg);
+        }
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+            const int64_t i = base + e;
+            const bool in = i < ev1;
+            EvOut o;
+            if (in) {
+                o = eval_event<Tin, PREC, K0, K1>(q[e], tg[e], g);
+            } else {
+                o.cls = -1;
+                o.bin = -1;
+                o.t2 = 0;
+                o.why = 0;
+                o.ct = 0.0;
+            }
+            bool listed = false, unres = false;
+            if (o.cls == CLS_DEFER) {
+                const uint32_t slot = atomicAdd(kp.xcount, 1u);
+                if (slot < kp.xcap) {
+                    kp.xlist[slot] = ((uint64_t)o.why << 60) | ((uint64_t)s << 40) | (uint64_t)i;
+                    listed = true;
+                } else {
+                    unres = true;
+                }
+            }
+            if (MODE == 1 && in) {
+                io.cls_out[i] = (int8_t)(unres ? CLS_UNRESOLVED : o.cls);
+                if (io.ct_out) io.ct_out[i] = o.ct;
+            }
+            const bool classified = o.cls >= 0 && o.cls < 4;
+            if (BINNED && classified && o.bin >= 0) atomicAdd(&myhist[(1 + o.bin) * 4 + o.cls], 1u);
+            if (MODE == 0) {
+                wc.c0 += wave_count(o.cls == CLS_I);
+                wc.c1 += wave_count(o.cls == CLS_II);
+                wc.c2 += wave_count(o.cls == CLS_III);
+                wc.c3 += wave_count(o.cls == CLS_IV);
+            }
+            // rare outcomes: one ballot decides whether the wave counts them
+            const bool oor = BINNED && classified && o.bin < 0;
+            const bool rare = (o.cls >= CLS_ZERO) || o.t2 || oor;
+            if (__ballot(rare)) {
+                wc.zero += wave_count(o.cls == CLS_ZERO);
+                wc.inv += wave_count(o.cls == CLS_INVALID);
+                wc.oor += wave_count(oor);
+                wc.t2 += wave_count(o.t2 != 0);
+                wc.t3 += wave_count(listed);
+                wc.un += wave_count(unres);
+            }
+        }
     }
 }
 
@@ -509,20 +614,20 @@ __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
         if (ev1 <= ev0) continue;
 
         // everything the event loop needs, read once per segment
-        const void *ptr[16];
+        SegIO io;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) ptr[k] = S->p[k];
-        const int8_t *tagp = S->tag;
-        const bool vec = S->vec != 0;
+        for (int k = 0; k < 16; ++k) io.ptr[k] = S->p[k];
+        io.tag = S->tag;
+        io.vec = S->vec != 0;
+        io.cls_out = S->cls_out;
+        io.ct_out = S->ct_out;
         uint64_t *counts = S->counts;
         uint64_t *stats = S->stats;
-        int8_t *cls_out = S->cls_out;
-        double *ct_out = S->ct_out;
         Seg g;
         g.sigma = S->sigma;
-        g.naxes = MODE == 0 ? S->naxes : 0;
-        g.kind0 = S->kind[0];
-        g.kind1 = S->kind[1];
+        const int naxes = MODE == 0 ? S->naxes : 0;
+        const int kind0 = naxes > 0 ? S->kind[0] : AX_NONE;
+        const int kind1 = naxes > 1 ? S->kind[1] : AX_NONE;
         g.nb0 = S->nbins[0];
         g.nb1 = S->nbins[1];
         g.slots0 = S->slots[0];
@@ -531,8 +636,8 @@ __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
         g.glo1 = S->guess_lo[1];
         g.ginv0 = S->guess_inv[0];
         g.ginv1 = S->guess_inv[1];
-        const int nd0 = g.naxes > 0 ? edge_doubles(g.kind0, g.nb0) : 0;
-        const int nd1 = g.naxes > 1 ? edge_doubles(g.kind1, g.nb1) : 0;
+        const int nd0 = naxes > 0 ? edge_doubles(kind0, g.nb0) : 0;
+        const int nd1 = naxes > 1 ? edge_doubles(kind1, g.nb1) : 0;
         const int eoff0 = S->eoff[0], eoff1 = S->eoff[1];
         const int nrow = (S->nbtot + 1) * 4;
         g.e0 = ecache;
@@ -543,75 +648,40 @@ __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
         for (int i = tid; i < nd1; i += nthr) ecache[nd0 + i] = kp.edges[eoff1 + i];
         __syncthreads();
 
-        uint32_t wc0 = 0, wc1 = 0, wc2 = 0, wc3 = 0, wzero = 0, winv = 0, woor = 0, wt2 = 0,
-                 wt3 = 0, wun = 0;
-        for (int64_t t0 = ev0; t0 < ev1; t0 += (int64_t)EPL * nthr) {
-            const int64_t base = t0 + (int64_t)EPL * tid;
-            Tin q[EPL][4][4];
-            int tg[EPL];
-            load_events<Tin, EPL>(ptr, tagp, base, vec, ev1, q, tg);
-#pragma unroll
-            for (int e = 0; e < EPL; ++e) {
-                const int64_t i = base + e;
-                const bool in = i < ev1;
-                EvOut o;
-                if (in) {
-                    o = eval_event<Tin, PREC>(q[e], tg[e], g);
-                } else {
-                    o.cls = -1;
-                    o.bin = -1;
-                    o.t2 = 0;
-                    o.why = 0;
-                    o.ct = 0.0;
-                }
-                bool listed = false, unres = false;
-                if (o.cls == CLS_DEFER) {
-                    const uint32_t slot = atomicAdd(kp.xcount, 1u);
-                    if (slot < kp.xcap) {
-                        kp.xlist[slot] = ((uint64_t)o.why << 60) | ((uint64_t)s << 40) | (uint64_t)i;
-                        listed = true;
-                    } else {
-                        unres = true;
-                    }
-                }
-                if (MODE == 1 && in) {
-                    cls_out[i] = (int8_t)(unres ? CLS_UNRESOLVED : o.cls);
-                    if (ct_out) ct_out[i] = o.ct;
-                }
-                if (MODE == 0 && o.cls >= 0 && o.cls < 4 && o.bin >= 0 && g.naxes > 0)
-                    atomicAdd(&myhist[(1 + o.bin) * 4 + o.cls], 1u);
-                if (MODE == 0) {
-                    wc0 += wave_count(o.cls == CLS_I);
-                    wc1 += wave_count(o.cls == CLS_II);
-                    wc2 += wave_count(o.cls == CLS_III);
-                    wc3 += wave_count(o.cls == CLS_IV);
-                }
-                // rare outcomes: one ballot decides whether the wave counts them
-                const bool rare = (o.cls >= CLS_ZERO) || o.t2 || (o.cls >= 0 && o.cls < 4 && o.bin < 0 &&
-                                                                 g.naxes > 0);
-                if (__ballot(rare)) {
-                    wzero += wave_count(o.cls == CLS_ZERO);
-                    winv += wave_count(o.cls == CLS_INVALID);
-                    woor += wave_count(o.cls >= 0 && o.cls < 4 && o.bin < 0 && g.naxes > 0);
-                    wt2 += wave_count(o.t2 != 0);
-                    wt3 += wave_count(listed);
-                    wun += wave_count(unres);
-                }
+        WaveCounts wc = { 0, 0, 0, 0, 0, 0, 0, 0, 0, 0 };
+#define TP_SEG(A, B) run_segment<Tin, PREC, MODE, EPL, A, B>(kp, s, io, g, ev0, ev1, myhist, wc)
+        if constexpr (MODE == 1) {
+            TP_SEG(AX_NONE, AX_NONE);
+        } else {
+            switch (kind0 * 4 + kind1) {
+            case AX_ABSPHI * 4 + AX_NONE: TP_SEG(AX_ABSPHI, AX_NONE); break;
+            case AX_MASS * 4 + AX_NONE: TP_SEG(AX_MASS, AX_NONE); break;
+            case AX_ABSCOS * 4 + AX_NONE: TP_SEG(AX_ABSCOS, AX_NONE); break;
+            case AX_ABSPHI * 4 + AX_MASS: TP_SEG(AX_ABSPHI, AX_MASS); break;
+            case AX_ABSPHI * 4 + AX_ABSCOS: TP_SEG(AX_ABSPHI, AX_ABSCOS); break;
+            case AX_MASS * 4 + AX_ABSPHI: TP_SEG(AX_MASS, AX_ABSPHI); break;
+            case AX_MASS * 4 + AX_MASS: TP_SEG(AX_MASS, AX_MASS); break;
+            case AX_MASS * 4 + AX_ABSCOS: TP_SEG(AX_MASS, AX_ABSCOS); break;
+            case AX_ABSCOS * 4 + AX_ABSPHI: TP_SEG(AX_ABSCOS, AX_ABSPHI); break;
+            case AX_ABSCOS * 4 + AX_MASS: TP_SEG(AX_ABSCOS, AX_MASS); break;
+            case AX_ABSCOS * 4 + AX_ABSCOS: TP_SEG(AX_ABSCOS, AX_ABSCOS); break;
+            default: TP_SEG(AX_NONE, AX_NONE); break;
             }
         }
+#undef TP_SEG
         if (lane == 0) {
             if (MODE == 0) {
-                atomicAdd(&myhist[0], wc0);
-                atomicAdd(&myhist[1], wc1);
-                atomicAdd(&myhist[2], wc2);
-                atomicAdd(&myhist[3], wc3);
+                atomicAdd(&myhist[0], wc.c0);
+                atomicAdd(&myhist[1], wc.c1);
+                atomicAdd(&myhist[2], wc.c2);
+                atomicAdd(&myhist[3], wc.c3);
             }
-            atomicAdd(&myhist[nrow + ST_ZERO], wzero);
-            atomicAdd(&myhist[nrow + ST_INVALID], winv);
-            atomicAdd(&myhist[nrow + ST_OOR], woor);
-            atomicAdd(&myhist[nrow + ST_TIER2], wt2);
-            atomicAdd(&myhist[nrow + ST_TIER3], wt3);
-            atomicAdd(&myhist[nrow + ST_UNRESOLVED], wun);
+            atomicAdd(&myhist[nrow + ST_ZERO], wc.zero);
+            atomicAdd(&myhist[nrow + ST_INVALID], wc.inv);
+            atomicAdd(&myhist[nrow + ST_OOR], wc.oor);
+            atomicAdd(&myhist[nrow + ST_TIER2], wc.t2);
+            atomicAdd(&myhist[nrow + ST_TIER3], wc.t3);
+            atomicAdd(&myhist[nrow + ST_UNRESOLVED], wc.un);
         }
         __syncthreads();
         for (int i = tid; i < ncnt; i += nthr) {

@@ -379,24 +379,34 @@ def lb_mass03_axis(ch: Channel, nbins: int = 8) -> Axis:
     return mass_axis((0, 3), m[0] + m[3], ch.parent - m[1] - m[2], nbins)
 
 
-def config_specs(config: int, scale: float = 1.0, seed_offset: int = 0):
-    """Sample specifications of workload ``config`` (1..5).
+# Named workloads: channel, size, storage, binning, injection.
+WORKLOADS = {
+    "lb_ppipipi_f64_1e5": "Lambda_b -> p pi- pi+ pi-, 1e5 events, float64 storage, 5 |Phi| bins (10 phi)",
+    "lb_ppipipi_1e7_phi12": "Lambda_b -> p pi- pi+ pi-, 1e7 events, 6 |Phi| bins (12 phi), sin(phi) injection",
+    "lb_pkpipi_1e8_phi10xm8": "Lambda_b -> p K- pi+ pi-, 1e8 events, 5 |Phi| x 8 m(p pi-), sin(2 phi) on M",
+    "lb_batch64_1e3to1e7": "64 Lambda_b samples (4 channels x 3 binnings), sizes log-uniform in [1e3, 1e7]",
+    "d0_kkpipi_5e8_m32x32": "D0 -> K+ K- pi+ pi-, 5e8 events, 32 m(K+K-) x 32 m(pi+pi-), sgn(sin phi) injection",
+}
+
+
+def workload_specs(name: str, scale: float = 1.0, seed_offset: int = 0):
+    """Sample specifications of a named workload (see WORKLOADS).
 
     scale < 1 shrinks every sample (same shapes, fewer events) for tests.
     """
     def N(x):
         return max(1, int(round(x * scale)))
-    if config == 1:
+    if name == "lb_ppipipi_f64_1e5":
         ch = CHANNELS["Lb_ppipipi"]
         return [SampleSpec(ch, N(1e5), 1 + seed_offset, [absphi_axis(10)], dtype=torch.float64)]
-    if config == 2:
+    if name == "lb_ppipipi_1e7_phi12":
         ch = CHANNELS["Lb_ppipipi"]
         return [SampleSpec(ch, N(1e7), 2 + seed_offset, [absphi_axis(12)], inj=INJ_SIN)]
-    if config == 3:
+    if name == "lb_pkpipi_1e8_phi10xm8":
         ch = CHANNELS["Lb_pKpipi"]
         return [SampleSpec(ch, N(1e8), 3 + seed_offset, [absphi_axis(10), lb_mass03_axis(ch)],
                            frac_m=0.52, inj=INJ_SIN2)]
-    if config == 4:
+    if name == "lb_batch64_1e3to1e7":
         rng = np.random.default_rng(4 + seed_offset)
         chans = ["Lb_ppipipi", "Lb_pKpipi", "Lb_ppiKK", "Lb_pKKK"]
         injs = {"Lb_ppipipi": INJ_SIN, "Lb_pKpipi": INJ_SIN2}
@@ -416,13 +426,13 @@ def config_specs(config: int, scale: float = 1.0, seed_offset: int = 0):
             specs.append(SampleSpec(ch, n, 1000 * (4 + seed_offset) + i, axes,
                                     inj=injs.get(ch.name, Injection())))
         return specs
-    if config == 5:
+    if name == "d0_kkpipi_5e8_m32x32":
         ch = CHANNELS["D0_KKpipi"]
         return [SampleSpec(ch, N(5e8), 5 + seed_offset,
                            [mass_axis((0, 1), 2 * M_K, M_D0 - 2 * M_PI, 32),
                             mass_axis((2, 3), 2 * M_PI, M_D0 - 2 * M_K, 32)],
                            inj=INJ_SGN)]
-    raise ValueError(config)
+    raise ValueError(f"unknown workload {name!r}; known: {sorted(WORKLOADS)}")
 
 
 def make_sample(spec: SampleSpec, device="cpu", chunk: int = 1 << 22) -> Sample:

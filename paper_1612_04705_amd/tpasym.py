@@ -14,7 +14,8 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtpasym.so")
+# TPASYM_LIB selects another build of the same library (e.g. an experimental variant)
+LIB_PATH = os.environ.get("TPASYM_LIB", os.path.join(_HERE, "libtpasym.so"))
 
 TP_F32, TP_F64 = 0, 1
 TP_PREC_F64, TP_PREC_F32_RECHECK = 0, 1

@@ -59,15 +59,17 @@ def check(tp, sample, ch, axes, precisions=None, label=""):
     return want, out
 
 
-@pytest.mark.parametrize("config,scale", [(1, 0.2), (2, 0.003), (3, 0.0004), (5, 0.0001)])
-def test_config_shapes(tp, config, scale):
-    for spec in synth.config_specs(config, scale):
+@pytest.mark.parametrize("workload,scale", [("lb_ppipipi_f64_1e5", 0.2), ("lb_ppipipi_1e7_phi12", 0.003),
+                                            ("lb_pkpipi_1e8_phi10xm8", 0.0004),
+                                            ("d0_kkpipi_5e8_m32x32", 0.0001)])
+def test_workload_shapes(tp, workload, scale):
+    for spec in synth.workload_specs(workload, scale):
         s = synth.make_sample(spec)
-        check(tp, s, spec.channel, spec.axes, label=f"config{config}")
+        check(tp, s, spec.channel, spec.axes, label=workload)
 
 
-def test_batch_config4_shape(tp):
-    specs = synth.config_specs(4, 0.002)
+def test_batch_workload_shape(tp):
+    specs = synth.workload_specs("lb_batch64_1e3to1e7", 0.002)
     items, wants = [], []
     for spec in specs:
         s = synth.make_sample(spec)
@@ -113,7 +115,7 @@ def test_compute_per_event_classes(tp):
 
 
 def test_asymmetries_from_gpu_counts(tp):
-    spec = synth.config_specs(2, 0.003)[0]
+    spec = synth.workload_specs("lb_ppipipi_1e7_phi12", 0.003)[0]
     s = synth.make_sample(spec)
     want, outs = check(tp, s, spec.channel, spec.axes)
     counts = outs[0][0]
@@ -190,7 +192,7 @@ def test_high_boost_needs_recheck(tp, gamma):
 
 
 def test_tuning_invariance(tp):
-    spec = synth.config_specs(5, 0.00005)[0]
+    spec = synth.workload_specs("d0_kkpipi_5e8_m32x32", 0.00005)[0]
     s = synth.make_sample(spec)
     ref = None
     for block in (256, 512):
@@ -204,7 +206,7 @@ def test_tuning_invariance(tp):
 
 
 def test_chunked_equals_whole(tp):
-    spec = synth.config_specs(3, 0.0003)[0]
+    spec = synth.workload_specs("lb_pkpipi_1e8_phi10xm8", 0.0003)[0]
     s = synth.make_sample(spec)
     ch = tp.channel(spec.channel.triple, spec.channel.planes)
     bn = tp.Binning(spec.axes)
