@@ -19,7 +19,7 @@
 #include "tp_kernel.h"
 
 namespace tpk {
-hipError_t launch_pass(int dtype, int prec, int mode, int epl, const KParams &kp, int grid, int block,
+hipError_t launch_pass(int dtype, int prec, int mode, int epl, int k0, int k1, const KParams &kp, int grid, int block,
                        size_t lds, hipStream_t st);
 hipError_t launch_exact(int dtype, int mode, const KParams &kp, int grid, hipStream_t st);
 }  // namespace tpk
@@ -64,12 +64,21 @@ struct Workspace {
     uint32_t *xdone = nullptr;
 };
 
+// Samples of one binning scheme: contiguous in the plan's sample table and in
+// the virtual event space; one pass launch each.
+struct Group {
+    int k0 = AX_NONE, k1 = AX_NONE;
+    int sbeg = 0, send = 0;
+    int64_t vbeg = 0, vend = 0;
+    int hist_stride = 0;
+    int edge_doubles = 0;
+};
+
 struct Plan {
     std::vector<KSample> hs;
     std::vector<double> hedges;
+    std::vector<Group> groups;
     int64_t vtotal = 0;
-    int hist_stride = 0;
-    int edge_doubles = 0;
     int dtype = 0;
     void *dbuf = nullptr;        // device: samples | edges
     void *pinned = nullptr;      // host copy source
@@ -238,6 +247,13 @@ int check_binning(const tp_binning *bn)
 void square_bounds(double e, double &lo, double &hi)
 {
     const double p = e * e;
+    if (p < 0x1p-969) {
+        // below 2^-969 the residual e*e - p need not be representable; the
+        // rounded square is within half an ulp, so its two neighbours bracket e^2
+        lo = std::fmax(std::nextafter(p, -INFINITY), 0.0);
+        hi = std::nextafter(p, INFINITY);
+        return;
+    }
     const double r = std::fma(e, e, -p);
     if (r > 0) {
         lo = p;
@@ -352,19 +368,38 @@ int build_plan(Device &d, const std::vector<Req> &rq, int mode, hipStream_t st, 
     }
     Plan *p = new Plan();
     p->dtype = rq.empty() ? 0 : rq[0].ev->dtype;
+    std::vector<KSample> ks(rq.size());
+    for (size_t r = 0; r < rq.size(); ++r)
+        fill_sample(ks[r], *rq[r].ev, *rq[r].ch, mode == 0 ? rq[r].bn : nullptr, rq[r].counts, rq[r].stats,
+                    rq[r].cls_out, rq[r].ct_out, p->hedges);
+    // order the samples by binning scheme (stable), one group per scheme
+    std::vector<size_t> order(rq.size());
+    for (size_t r = 0; r < order.size(); ++r) order[r] = r;
+    auto scheme = [&](size_t r) { return ks[r].kind[0] * 4 + ks[r].kind[1]; };
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return scheme(a) < scheme(b); });
     int64_t v = 0;
-    for (const Req &r : rq) {
-        KSample k;
-        fill_sample(k, *r.ev, *r.ch, mode == 0 ? r.bn : nullptr, r.counts, r.stats, r.cls_out, r.ct_out,
-                    p->hedges);
+    for (size_t r : order) {
+        KSample k = ks[r];
         k.vstart = v;
-        v += (r.ev->n + 3) & ~int64_t(3);
+        v += (k.n + 3) & ~int64_t(3);
+        const int sidx = (int)p->hs.size();
         p->hs.push_back(k);
+        if (p->groups.empty() || p->groups.back().k0 != k.kind[0] || p->groups.back().k1 != k.kind[1]) {
+            Group g;
+            g.k0 = k.kind[0];
+            g.k1 = k.kind[1];
+            g.sbeg = sidx;
+            g.vbeg = k.vstart;
+            p->groups.push_back(g);
+        }
+        Group &g = p->groups.back();
+        g.send = sidx + 1;
+        g.vend = v;
         const int stride = (k.nbtot + 1) * 4 + NSTAT;
-        p->hist_stride = std::max(p->hist_stride, stride);
+        g.hist_stride = std::max(g.hist_stride, stride);
         int ed = 0;
         for (int a = 0; a < k.naxes; ++a) ed += edge_doubles(k.kind[a], k.nbins[a]);
-        p->edge_doubles = std::max(p->edge_doubles, ed);
+        g.edge_doubles = std::max(g.edge_doubles, ed);
     }
     p->vtotal = v;
     if (p->hedges.empty()) p->hedges.push_back(0.0);
@@ -425,38 +460,7 @@ int launch_plan(Device &d, const Plan &p, const tp_tuning &tu_in, int prec, int 
     defaults(d, tu, p.vtotal);
     if (p.vtotal == 0) return TP_OK;
     const int epl = p.dtype == TP_F32 ? tu.unroll : std::min(tu.unroll, 2);
-    int copies = tu.lds_copies;
-    size_t hist_bytes = 0;
-    for (;;) {
-        hist_bytes = ((size_t)copies * p.hist_stride * 4 + 15) & ~size_t(15);
-        if (hist_bytes + (size_t)p.edge_doubles * 8 <= LDS_LIMIT || copies == 1) break;
-        --copies;
-    }
-    const size_t lds = hist_bytes + (size_t)p.edge_doubles * 8;
-    if (lds > LDS_LIMIT) return fail(TP_ERANGE, "histogram does not fit in LDS");
     const int64_t tile = (int64_t)epl * tu.block;
-    int64_t grid = (int64_t)d.cus * tu.wg_per_cu;
-    const int64_t need = (p.vtotal + tile - 1) / tile;
-    if (grid > need) grid = need;
-    if (grid < 1) grid = 1;
-    int64_t range = (p.vtotal + grid - 1) / grid;
-    range = (range + tile - 1) / tile * tile;
-    grid = (p.vtotal + range - 1) / range;
-    KParams kp;
-    std::memset(&kp, 0, sizeof kp);
-    kp.samples = p.dsamples;
-    kp.nsamples = (int32_t)p.hs.size();
-    kp.lds_copies = copies;
-    kp.hist_stride = p.hist_stride;
-    kp.edge_doubles = p.edge_doubles;
-    kp.range = range;
-    kp.vtotal = p.vtotal;
-    kp.edges = p.dedges;
-    kp.xlist = ws.xlist;
-    kp.xcount = ws.xcount;
-    kp.xdone = ws.xdone;
-    kp.xcap = XCAP;
-    kp.mode = mode;
     const bool timed = g_timing.on && !g_timing.ring.empty();
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
@@ -465,7 +469,44 @@ int launch_plan(Device &d, const Plan &p, const tp_tuning &tu_in, int prec, int 
         e1 = pr.second;
         TP_HIP(hipEventRecord(e0, st));
     }
-    TP_HIP(launch_pass(p.dtype, prec, mode, epl, kp, (int)grid, tu.block, lds, st));
+    KParams kp;
+    std::memset(&kp, 0, sizeof kp);
+    kp.samples = p.dsamples;
+    kp.edges = p.dedges;
+    kp.xlist = ws.xlist;
+    kp.xcount = ws.xcount;
+    kp.xdone = ws.xdone;
+    kp.xcap = XCAP;
+    kp.mode = mode;
+    for (const Group &g : p.groups) {
+        const int64_t nv = g.vend - g.vbeg;
+        if (nv <= 0) continue;
+        int copies = tu.lds_copies;
+        size_t hist_bytes = 0;
+        for (;;) {
+            hist_bytes = ((size_t)copies * g.hist_stride * 4 + 15) & ~size_t(15);
+            if (hist_bytes + (size_t)g.edge_doubles * 8 <= LDS_LIMIT || copies == 1) break;
+            --copies;
+        }
+        const size_t lds = hist_bytes + (size_t)g.edge_doubles * 8;
+        if (lds > LDS_LIMIT) return fail(TP_ERANGE, "histogram does not fit in LDS");
+        int64_t grid = (int64_t)d.cus * tu.wg_per_cu;
+        const int64_t need = (nv + tile - 1) / tile;
+        if (grid > need) grid = need;
+        if (grid < 1) grid = 1;
+        int64_t range = (nv + grid - 1) / grid;
+        range = (range + tile - 1) / tile * tile;
+        grid = (nv + range - 1) / range;
+        kp.sbeg = g.sbeg;
+        kp.send = g.send;
+        kp.vbeg = g.vbeg;
+        kp.vend = g.vend;
+        kp.lds_copies = copies;
+        kp.hist_stride = g.hist_stride;
+        kp.edge_doubles = g.edge_doubles;
+        kp.range = range;
+        TP_HIP(launch_pass(p.dtype, prec, mode, epl, g.k0, g.k1, kp, (int)grid, tu.block, lds, st));
+    }
     if (timed) {
         TP_HIP(hipEventRecord(e1, st));
         g_timing.next = (g_timing.next + 1) % g_timing.ring.size();

@@ -37,21 +37,23 @@ struct KSample {
     double guess_inv[2];      // MASS: 1 / bin width
 };
 
-// Launch parameters (kernel argument).
+// Launch parameters (kernel argument).  One pass launch covers the samples
+// [sbeg, send) -- all of one binning scheme -- whose virtual events are
+// [vbeg, vend); the deferral list and the edge table are shared by all.
 struct KParams {
     const KSample *samples;
-    int32_t nsamples;
+    int32_t sbeg, send;
     int32_t lds_copies;
     int32_t hist_stride;      // uint32 counters per LDS copy
     int32_t edge_doubles;     // doubles of edge data cached in LDS per segment (max over samples)
+    int32_t mode;             // 0 = counts, 1 = per-event outputs
     int64_t range;            // virtual events per workgroup (multiple of 4)
-    int64_t vtotal;           // total virtual events
+    int64_t vbeg, vend;       // virtual event range of this launch
     const double *edges;      // edge table
     uint64_t *xlist;          // deferred events: (stage << 60) | (sample << 40) | event
     uint32_t *xcount;         // number of listed events
     uint32_t *xdone;          // finished exact-tier workgroups (last one resets)
     uint32_t xcap;
-    int32_t mode;             // 0 = counts, 1 = per-event outputs
 };
 
 // Edge data layout per axis (at eoff):

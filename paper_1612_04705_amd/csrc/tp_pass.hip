@@ -63,18 +63,27 @@ __device__ __forceinline__ float minor32(float a, float b, float c, float d)
     return f + e;
 }
 
-// Laplace expansion of det[x0; x1; x2; x3] on the row pairs (0,1) | (2,3):
-// column pairs k = (0,1) (0,2) (0,3) (1,2) (1,3) (2,3), complement 5 - k,
-// signs + - + + - +.
+// 2x2 minors of two rows a, b: m[k] = a_i b_j - a_j b_i for the column pairs
+// k = (0,1) (0,2) (0,3) (1,2) (1,3) (2,3) -- the six components of the bivector a^b.
 template <bool EXACT_PRODUCTS>
-__device__ __forceinline__ bool det_f64(const double x[4][4], double &det)
+__device__ __forceinline__ void minors_f64(const double (&a)[4], const double (&b)[4], double (&m)[6])
 {
-    double m01[6], m23[6];
-#define TP_M(k, a, b)                                                          \
-    m01[k] = minor64<EXACT_PRODUCTS>(x[0][a], x[0][b], x[1][a], x[1][b]);      \
-    m23[k] = minor64<EXACT_PRODUCTS>(x[2][a], x[2][b], x[3][a], x[3][b]);
-    TP_M(0, 0, 1) TP_M(1, 0, 2) TP_M(2, 0, 3) TP_M(3, 1, 2) TP_M(4, 1, 3) TP_M(5, 2, 3)
-#undef TP_M
+    m[0] = minor64<EXACT_PRODUCTS>(a[0], a[1], b[0], b[1]);
+    m[1] = minor64<EXACT_PRODUCTS>(a[0], a[2], b[0], b[2]);
+    m[2] = minor64<EXACT_PRODUCTS>(a[0], a[3], b[0], b[3]);
+    m[3] = minor64<EXACT_PRODUCTS>(a[1], a[2], b[1], b[2]);
+    m[4] = minor64<EXACT_PRODUCTS>(a[1], a[3], b[1], b[3]);
+    m[5] = minor64<EXACT_PRODUCTS>(a[2], a[3], b[2], b[3]);
+}
+
+// Laplace expansion of det[x0; x1; x2; x3] on the row pairs (0,1) | (2,3) from
+// the minors of both pairs: column pair k pairs with its complement 5 - k,
+// signs + - + + - +.  With exact products each minor is correctly rounded and
+// |s - det| <= 8.1 u S; with Kahan minors (float64 inputs) 10.1 u S plus
+// underflow terms, S = sum |m01_k| |m23_(5-k)|.
+template <bool EXACT_PRODUCTS>
+__device__ __forceinline__ bool det_f64(const double (&m01)[6], const double (&m23)[6], double &det)
+{
     double s = m01[0] * m23[5];
     s = fma(-m01[1], m23[4], s);
     s = fma(m01[2], m23[3], s);
@@ -84,7 +93,6 @@ __device__ __forceinline__ bool det_f64(const double x[4][4], double &det)
     double S = dabs(m01[0]) * dabs(m23[5]);
 #pragma unroll
     for (int k = 1; k < 6; ++k) S = fma(dabs(m01[k]), dabs(m23[5 - k]), S);
-    // |s - det| <= 8.1 u S (exact products) / 10.1 u S + underflow terms (Kahan minors)
     const double bound = EXACT_PRODUCTS ? (10.0 * U64) * S : fma(12.0 * U64, S, 0x1p-160);
     det = s;
     return dabs(s) > bound;
@@ -122,7 +130,11 @@ __device__ __forceinline__ double mink(const double a[4], const double b[4])
     return fma(-a[3], b[3], fma(-a[2], b[2], fma(-a[1], b[1], a[0] * b[0])));
 }
 
-__device__ __forceinline__ double dmax(double a, double b) { return __builtin_fmax(a, b); }
+// Absolute floor added to every float64 error bound: it covers the absolute
+// (not relative) rounding errors of results that fall below the normal range,
+// so a bound stays valid for inputs of any magnitude; events that small simply
+// defer to the later tiers.
+constexpr double TINY = 0x1p-1000;
 
 // 1/sqrt(D), D > 0: hardware estimate r0, one Newton step, and the residual
 // rho = 1 - D r0^2 of the estimate.  With |rho| <= 2^-10 the result satisfies
@@ -147,56 +159,55 @@ __device__ __forceinline__ double ratio_eps(double v, double r, double rel, doub
     return fma(1.01, fma(dabs(v), rel + U64, fma(eY, r, 0.54 * eD * r * r)), 3.0 * U64);
 }
 
-// Plane angle between kernel planes (0,1) and (2,3): cos Phi = X / sqrt(N1 N2).
-// edges: c_0 = 1 > c_1 > ... > c_n = -1; returns #{k in 1..n-1 : cos Phi <= c_k}.
-// Error bounds: |P.p_a^ - P.p_a| <= 7.2 u W w_a, |M^2^ - M^2| <= 10.2 u W^2,
-// |d_ab^ - d_ab| <= kdot u w_a w_b (w_a = L1 norm of p_a, W = sum of w_a); one
-// bound eG serves every G_ab, built from the largest |P.p_a|, |d_ab| and w_a.
-__device__ __forceinline__ int bin_absphi(const double x[4][4], double W, double wmax, double M2,
-                                          double kdot, const double *edges, int n, bool &sure)
+// Plane angle between kernel planes (0,1) and (2,3) from the bivectors
+// B1 = p0^p1, B2 = p2^p3 (their minors m01, m23).  The covector C with
+// det[c; P; a; b] = c.C for every c is, in the M rest frame, (0, +-M (p*_a x p*_b)),
+// so with the Minkowski products
+//   X = C1.C2 = -M^2 n1.n2,  S_i = C_i.C_i = -M^2 |n_i|^2,  cos Phi = -X / sqrt(S1 S2),
+// n_i the rest-frame plane normals.  The minors are shared with the sign.
+// Error bounds (W = L1 norm of all components, so |P_c| <= W):
+//   |P^_c - P_c| <= 2.01 u W;  |m^ - m| <= k u |m^| (k = 1 correctly rounded
+//   minors of float inputs, 2 Kahan minors of float64 inputs);
+//   each C_mu is a three-term fused sum: |C^_mu - C_mu| <= (3.02 + 2.01 + k) u W sum|m^|
+//   <= 7.2 u W sum|m^| = eC;
+//   |X^ - X| <= eC2 A1 + eC1 A2 + 4 eC1 eC2 + 4.01 u A1 A2 (A = L1 norm of C^),
+//   |S^ - S| <= 2 eC A + 4 eC^2 + 4.01 u A^2.
+// S1, S2 < 0 certified, then D = S1 S2 and the ratio as for the other angles.
+__device__ __forceinline__ void covector(const double (&P)[4], const double (&m)[6], double (&C)[4])
 {
-    const double d00 = mink(x[0], x[0]), d11 = mink(x[1], x[1]), d22 = mink(x[2], x[2]), d33 = mink(x[3], x[3]);
-    const double d01 = mink(x[0], x[1]), d02 = mink(x[0], x[2]), d03 = mink(x[0], x[3]);
-    const double d12 = mink(x[1], x[2]), d13 = mink(x[1], x[3]), d23 = mink(x[2], x[3]);
-    const double P0 = (d00 + d01) + (d02 + d03);
-    const double P1 = (d01 + d11) + (d12 + d13);
-    const double P2 = (d02 + d12) + (d22 + d23);
-    const double P3 = (d03 + d13) + (d23 + d33);
-#define TP_G(a, b, dab) fma(P##a, P##b, -(M2 * dab))
-    const double G00 = TP_G(0, 0, d00), G11 = TP_G(1, 1, d11), G22 = TP_G(2, 2, d22), G33 = TP_G(3, 3, d33);
-    const double G01 = TP_G(0, 1, d01), G23 = TP_G(2, 3, d23);
-    const double G02 = TP_G(0, 2, d02), G13 = TP_G(1, 3, d13), G03 = TP_G(0, 3, d03), G12 = TP_G(1, 2, d12);
-#undef TP_G
-    const double PPm = dmax(dmax(dabs(P0), dabs(P1)), dmax(dabs(P2), dabs(P3)));
-    const double dm = dmax(dmax(dmax(dabs(d00), dabs(d11)), dmax(dabs(d22), dabs(d33))),
-                           dmax(dmax(dmax(dabs(d01), dabs(d02)), dmax(dabs(d03), dabs(d12))),
-                                dmax(dabs(d13), dabs(d23))));
-    const double aM = dabs(M2);
-    const double uWW = U64 * W * W;
-    // eG >= |G^ - G| for every pair (first-order terms, second-order 94 u^2 W^4, roundings)
-    const double eG = fma(U64, fma((14.4 * W) * wmax, PPm, fma(10.2 * W * W, dm,
-                          fma((kdot * wmax) * wmax, aM, 2.01 * fma(PPm, PPm, aM * dm)))),
-                          94.0 * uWW * uWW);
-    const double u2 = 2.01 * U64;
-    const double p1 = G03 * G12;
-    const double X = fma(G02, G13, -p1);
-    const double eX = fma(eG, ((dabs(G02) + dabs(G13)) + (dabs(G03) + dabs(G12))) + 2.0 * eG,
-                          u2 * fma(dabs(G02), dabs(G13), dabs(p1)));
-    const double q1 = G01 * G01;
-    const double N1 = fma(G00, G11, -q1);
-    const double eN1 = fma(eG, (dabs(G00) + dabs(G11)) + (2.0 * dabs(G01) + 2.0 * eG),
-                           u2 * fma(dabs(G00), dabs(G11), q1));
-    const double q2 = G23 * G23;
-    const double N2 = fma(G22, G33, -q2);
-    const double eN2 = fma(eG, (dabs(G22) + dabs(G33)) + (2.0 * dabs(G23) + 2.0 * eG),
-                           u2 * fma(dabs(G22), dabs(G33), q2));
-    bool ok = (N1 > eN1) && (N2 > eN2);
-    const double D = N1 * N2;
-    const double eD = fma(N1 + eN1, eN2, fma(N2, eN1, U64 * D));
+    C[0] = fma(P[3], m[3], fma(-P[2], m[4], P[1] * m[5]));
+    C[1] = fma(-P[3], m[1], fma(P[2], m[2], -(P[0] * m[5])));
+    C[2] = fma(P[3], m[0], fma(-P[1], m[2], P[0] * m[4]));
+    C[3] = fma(-P[2], m[0], fma(P[1], m[1], -(P[0] * m[3])));
+}
+
+__device__ __forceinline__ int bin_absphi_bv(const double (&m01)[6], const double (&m23)[6], const double (&P)[4],
+                                             double W, const double *edges, int n, bool &sure)
+{
+    double C1[4], C2[4];
+    covector(P, m01, C1);
+    covector(P, m23, C2);
+    const double M1 = ((dabs(m01[0]) + dabs(m01[1])) + (dabs(m01[2]) + dabs(m01[3]))) + (dabs(m01[4]) + dabs(m01[5]));
+    const double M2s = ((dabs(m23[0]) + dabs(m23[1])) + (dabs(m23[2]) + dabs(m23[3]))) + (dabs(m23[4]) + dabs(m23[5]));
+    const double eabs = fma(TINY, W, TINY);
+    const double eC1 = fma((7.2 * U64) * W, M1, eabs);
+    const double eC2 = fma((7.2 * U64) * W, M2s, eabs);
+    const double A1 = (dabs(C1[0]) + dabs(C1[1])) + (dabs(C1[2]) + dabs(C1[3]));
+    const double A2 = (dabs(C2[0]) + dabs(C2[1])) + (dabs(C2[2]) + dabs(C2[3]));
+    const double X = fma(-C1[3], C2[3], fma(-C1[2], C2[2], fma(-C1[1], C2[1], C1[0] * C2[0])));
+    const double S1 = fma(-C1[3], C1[3], fma(-C1[2], C1[2], fma(-C1[1], C1[1], C1[0] * C1[0])));
+    const double S2 = fma(-C2[3], C2[3], fma(-C2[2], C2[2], fma(-C2[1], C2[1], C2[0] * C2[0])));
+    const double u4 = 4.02 * U64;
+    const double eX = fma(eC2, A1, fma(eC1, A2, fma(4.0 * eC1, eC2, fma(u4 * A1, A2, TINY))));
+    const double eS1 = fma(2.0 * eC1, A1, fma(4.0 * eC1, eC1, fma(u4 * A1, A1, TINY)));
+    const double eS2 = fma(2.0 * eC2, A2, fma(4.0 * eC2, eC2, fma(u4 * A2, A2, TINY)));
+    bool ok = (-S1 > eS1) && (-S2 > eS2);
+    const double D = S1 * S2;
+    const double eD = fma(dabs(S1) + eS1, eS2, fma(dabs(S2), eS1, fma(U64, D, TINY)));
     ok = ok && (eD <= 0.25 * D);
     double rel;
     const double r = rsqrt_cert(D, rel, ok);
-    const double v = X * r;
+    const double v = -X * r;
     const double eps = ratio_eps(v, r, rel, eX, eD);
     const double vhi = v + eps, vlo = v - eps;
     int bin = 0;
@@ -244,15 +255,15 @@ __device__ __forceinline__ int bin_abscos(const double x[4][4], const double w[4
     const double eds = (kdot * U64) * ws * ws;
     const double Nn = fma(PPs, EP, -(M2 * Es));
     const double eNn = fma(dabs(PPs) + ePP, eEP, fma(dabs(EP), ePP,
-                       fma(dabs(Es), eM, u2 * (dabs(PPs * EP) + dabs(M2 * Es)))));
+                       fma(dabs(Es), eM, fma(u2, dabs(PPs * EP) + dabs(M2 * Es), TINY))));
     const double A = fma(PPs, PPs, -(M2 * dss));
     const double eA = fma(2.0 * dabs(PPs) + ePP, ePP, fma(dabs(M2) + eM, eds,
-                      fma(dabs(dss), eM, u2 * (PPs * PPs + dabs(M2 * dss)))));
+                      fma(dabs(dss), eM, fma(u2, PPs * PPs + dabs(M2 * dss), TINY))));
     const double B = fma(P[3], P[3], fma(P[2], P[2], P[1] * P[1]));
-    const double eB = fma(6.1 * U64 * W, W, (3.1 * U64) * B);
+    const double eB = fma(6.1 * U64 * W, W, fma(3.1 * U64, B, TINY));
     bool ok = (A > eA) && (B > eB);
     const double D = A * B;
-    const double eD = fma(A + eA, eB, fma(B, eA, U64 * D));
+    const double eD = fma(A + eA, eB, fma(B, eA, fma(U64, D, TINY)));
     ok = ok && (eD <= 0.25 * D);
     double rel;
     const double r = rsqrt_cert(D, rel, ok);
@@ -285,7 +296,7 @@ __device__ __forceinline__ int bin_mass(const double x[4][4], const double w[4],
             WS += w[s];
         }
     const double m2 = fma(-S[3], S[3], fma(-S[2], S[2], fma(-S[1], S[1], S[0] * S[0])));
-    const double em = (12.4 * U64) * WS * WS;
+    const double em = fma((12.4 * U64) * WS, WS, TINY);
     const double *sqlo = ed, *sqhi = ed + (n + 1);
     const double mlo = m2 - em, mhi = m2 + em;
     // guess on a uniform grid in m, then certify against the two neighbouring edges
@@ -320,12 +331,13 @@ struct Seg {
 
 // One axis of compile-time kind KIND: bin index, or -1 (out of range).
 template <int KIND, bool EXACTP>
-__device__ __forceinline__ int axis_bin(const double (&x)[4][4], const double (&w)[4], double W, double wmax,
+__device__ __forceinline__ int axis_bin(const double (&x)[4][4], const double (&w)[4], double W,
+                                        const double (&m01)[6], const double (&m23)[6],
                                         const double (&P)[4], double M2, double eM, int nb, int sl,
                                         const double *ed, double glo, double ginv, bool &sure)
 {
     constexpr double KDOT = EXACTP ? 3.02 : 4.02;
-    if constexpr (KIND == AX_ABSPHI) return bin_absphi(x, W, wmax, M2, KDOT, ed, nb, sure);
+    if constexpr (KIND == AX_ABSPHI) return bin_absphi_bv(m01, m23, P, W, ed, nb, sure);
     else if constexpr (KIND == AX_MASS) return bin_mass(x, w, sl, ed, nb, glo, ginv, sure);
     else return bin_abscos(x, w, W, P, M2, eM, KDOT, sl, ed, nb, sure);
 }
@@ -352,7 +364,7 @@ __device__ __forceinline__ EvOut eval_event(const Tin (&q)[4][4], int tag, const
 #pragma unroll
         for (int c = 0; c < 4; ++c) x[s][c] = (double)q[s][c];
 
-    // validity: E_P > 0 and M^2 > 0 (|M^2 computed - M^2| <= 10.1 u W^2)
+    // validity: E_P > 0 and M^2 > 0 (|M^2 computed - M^2| <= 10.1 u W^2 + underflow)
     double w[4], P[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) w[s] = (dabs(x[s][0]) + dabs(x[s][1])) + (dabs(x[s][2]) + dabs(x[s][3]));
@@ -361,12 +373,18 @@ __device__ __forceinline__ EvOut eval_event(const Tin (&q)[4][4], int tag, const
     for (int c = 0; c < 4; ++c) P[c] = (x[0][c] + x[1][c]) + (x[2][c] + x[3][c]);
     const double M2 = fma(-P[3], P[3], fma(-P[2], P[2], fma(-P[1], P[1], P[0] * P[0])));
     const double Emin = fmin(fmin(x[0][0], x[1][0]), fmin(x[2][0], x[3][0]));
-    if (!(Emin >= 0.0 && P[0] > 0.0 && M2 > (11.0 * U64) * W * W)) return o;
+    if (!(Emin >= 0.0 && P[0] > 0.0 && M2 > fma((11.0 * U64) * W, W, TINY))) return o;
 
-    // sign of the triple product
+    // Sign of the triple product.  The plane-angle bins need the float64
+    // minors (the bivectors p0^p1, p2^p3) anyway, and the determinant from them
+    // costs a dozen operations, less than the float32 contraction: so the
+    // float32 sign with float64 recheck runs only when no plane angle is binned.
+    constexpr bool NEED_BV = K0 == AX_ABSPHI || K1 == AX_ABSPHI;
+    constexpr bool F32_SIGN = PREC == 1 && !NEED_BV;
+    double m01[6], m23[6];
     double det;
     bool sure;
-    if constexpr (PREC == 1) {
+    if constexpr (F32_SIGN) {
         float det32;
         float qf[4][4];
 #pragma unroll
@@ -376,11 +394,15 @@ __device__ __forceinline__ EvOut eval_event(const Tin (&q)[4][4], int tag, const
         sure = det_f32(qf, det32);
         det = (double)det32;
         if (!sure) {
+            minors_f64<EXACTP>(x[0], x[1], m01);
+            minors_f64<EXACTP>(x[2], x[3], m23);
             o.t2 = 1;
-            sure = det_f64<EXACTP>(x, det);
+            sure = det_f64<EXACTP>(m01, m23, det);
         }
     } else {
-        sure = det_f64<EXACTP>(x, det);
+        minors_f64<EXACTP>(x[0], x[1], m01);
+        minors_f64<EXACTP>(x[2], x[3], m23);
+        sure = det_f64<EXACTP>(m01, m23, det);
     }
     const double ct = g.sigma > 0 ? det : -det;
     o.ct = ct;
@@ -393,16 +415,15 @@ __device__ __forceinline__ EvOut eval_event(const Tin (&q)[4][4], int tag, const
         return o;
     } else {
         const double eM = (10.2 * U64) * W * W;
-        double wmax = 0.0;
-        if constexpr (K0 == AX_ABSPHI || K1 == AX_ABSPHI) wmax = dmax(dmax(w[0], w[1]), dmax(w[2], w[3]));
         bool bsure = true;
         o.why = 3;
-        const int j0 = axis_bin<K0, EXACTP>(x, w, W, wmax, P, M2, eM, g.nb0, g.slots0, g.e0, g.glo0, g.ginv0, bsure);
+        const int j0 = axis_bin<K0, EXACTP>(x, w, W, m01, m23, P, M2, eM, g.nb0, g.slots0, g.e0, g.glo0, g.ginv0,
+                                            bsure);
         bool oor = j0 < 0;
         int bin = j0 < 0 ? 0 : j0;
         if constexpr (K1 != AX_NONE) {
             if (bsure) o.why = 4;
-            const int j1 = axis_bin<K1, EXACTP>(x, w, W, wmax, P, M2, eM, g.nb1, g.slots1, g.e1, g.glo1,
+            const int j1 = axis_bin<K1, EXACTP>(x, w, W, m01, m23, P, M2, eM, g.nb1, g.slots1, g.e1, g.glo1,
                                                 g.ginv1, bsure);
             oor = oor || j1 < 0;
             bin = bin * g.nb1 + (j1 < 0 ? 0 : j1);
@@ -497,89 +518,109 @@ struct SegIO {
     bool vec;
 };
 
-// The event loop of one segment (events [ev0, ev1) of sample s) for one
-// binning scheme.
+// One tile: EPL consecutive events per lane starting at ``base``.
 template <typename Tin, int PREC, int MODE, int EPL, int K0, int K1>
-__device__ __forceinline__ void run_segment(const KParams &kp, int s, const SegIO &io, const Seg &g,
-                                            int64_t ev0, int64_t ev1, uint32_t *myhist, WaveCounts &wc)
+__device__ __forceinline__ void process_tile(const KParams &kp, int s, const SegIO &io, const Seg &g,
+                                             const Tin (&q)[EPL][4][4], const int (&tg)[EPL], int64_t base,
+                                             int64_t ev1, uint32_t *myhist, WaveCounts &wc)
 {
-    const int tid = threadIdx.x;
-    const int nthr = blockDim.x;
     constexpr bool BINNED = MODE == 0 && K0 != AX_NONE;
-    // Register double buffer: the next tile's inputs are requested before the
-    // current tile is evaluated, so every wave keeps loads in flight.
-    constexpr bool PF = EPL <= 2;
-    const int64_t step = (int64_t)EPL * nthr;
-    Tin qn[EPL][4][4];
-    int tgn[EPL];
-    if (PF && ev0 < ev1) load_events<Tin, EPL>(io.ptr, io.tag, ev0 + (int64_t)EPL * tid, io.vec, ev1, qn, tgn);
-    for (int64_t t0 = ev0; t0 < ev1; t0 += step) {
-        const int64_t base = t0 + (int64_t)EPL * tid;
-        Tin q[EPL][4][4];
-        int tg[EPL];
-        if constexpr (PF) {
 #pragma unroll
-            for (int e = 0; e < EPL; ++e) {
-                tg[e] = tgn[e];
-#pragma unroll
-                for (int k = 0; k < 16; ++k) q[e][k >> 2][k & 3] = qn[e][k >> 2][k & 3];
-            }
-            if (t0 + step < ev1) load_events<Tin, EPL>(io.ptr, io.tag, base + step, io.vec, ev1, qn, tgn);
+    for (int e = 0; e < EPL; ++e) {
+        const int64_t i = base + e;
+        const bool in = i < ev1;
+        EvOut o;
+        if (in) {
+            o = eval_event<Tin, PREC, K0, K1>(q[e], tg[e], g);
         } else {
-            load_events<Tin, EPL>(io.ptr, io.tag, base, io.vec, ev1, q, tg);
+            o.cls = -1;
+            o.bin = -1;
+            o.t2 = 0;
+            o.why = 0;
+            o.ct = 0.0;
         }
-#pragma unroll
-        for (int e = 0; e < EPL; ++e) {
-            const int64_t i = base + e;
-            const bool in = i < ev1;
-            EvOut o;
-            if (in) {
-                o = eval_event<Tin, PREC, K0, K1>(q[e], tg[e], g);
+        bool listed = false, unres = false;
+        if (o.cls == CLS_DEFER) {
+            const uint32_t slot = atomicAdd(kp.xcount, 1u);
+            if (slot < kp.xcap) {
+                kp.xlist[slot] = ((uint64_t)o.why << 60) | ((uint64_t)s << 40) | (uint64_t)i;
+                listed = true;
             } else {
-                o.cls = -1;
-                o.bin = -1;
-                o.t2 = 0;
-                o.why = 0;
-                o.ct = 0.0;
+                unres = true;
             }
-            bool listed = false, unres = false;
-            if (o.cls == CLS_DEFER) {
-                const uint32_t slot = atomicAdd(kp.xcount, 1u);
-                if (slot < kp.xcap) {
-                    kp.xlist[slot] = ((uint64_t)o.why << 60) | ((uint64_t)s << 40) | (uint64_t)i;
-                    listed = true;
-                } else {
-                    unres = true;
-                }
-            }
-            if (MODE == 1 && in) {
-                io.cls_out[i] = (int8_t)(unres ? CLS_UNRESOLVED : o.cls);
-                if (io.ct_out) io.ct_out[i] = o.ct;
-            }
-            const bool classified = o.cls >= 0 && o.cls < 4;
-            if (BINNED && classified && o.bin >= 0) atomicAdd(&myhist[(1 + o.bin) * 4 + o.cls], 1u);
-            if (MODE == 0) {
-                wc.c0 += wave_count(o.cls == CLS_I);
-                wc.c1 += wave_count(o.cls == CLS_II);
-                wc.c2 += wave_count(o.cls == CLS_III);
-                wc.c3 += wave_count(o.cls == CLS_IV);
-            }
-            // rare outcomes: one ballot decides whether the wave counts them
-            const bool oor = BINNED && classified && o.bin < 0;
-            const bool rare = (o.cls >= CLS_ZERO) || o.t2 || oor;
-            if (__ballot(rare)) {
-                wc.zero += wave_count(o.cls == CLS_ZERO);
-                wc.inv += wave_count(o.cls == CLS_INVALID);
-                wc.oor += wave_count(oor);
-                wc.t2 += wave_count(o.t2 != 0);
-                wc.t3 += wave_count(listed);
-                wc.un += wave_count(unres);
-            }
+        }
+        if (MODE == 1 && in) {
+            io.cls_out[i] = (int8_t)(unres ? CLS_UNRESOLVED : o.cls);
+            if (io.ct_out) io.ct_out[i] = o.ct;
+        }
+        const bool classified = o.cls >= 0 && o.cls < 4;
+        if (BINNED && classified && o.bin >= 0) atomicAdd(&myhist[(1 + o.bin) * 4 + o.cls], 1u);
+        if (MODE == 0) {
+            wc.c0 += wave_count(o.cls == CLS_I);
+            wc.c1 += wave_count(o.cls == CLS_II);
+            wc.c2 += wave_count(o.cls == CLS_III);
+            wc.c3 += wave_count(o.cls == CLS_IV);
+        }
+        // rare outcomes: one ballot decides whether the wave counts them
+        const bool oor = BINNED && classified && o.bin < 0;
+        const bool rare = (o.cls >= CLS_ZERO) || o.t2 || oor;
+        if (__ballot(rare)) {
+            wc.zero += wave_count(o.cls == CLS_ZERO);
+            wc.inv += wave_count(o.cls == CLS_INVALID);
+            wc.oor += wave_count(oor);
+            wc.t2 += wave_count(o.t2 != 0);
+            wc.t3 += wave_count(listed);
+            wc.un += wave_count(unres);
         }
     }
 }
 
-template <typename Tin, int PREC, int MODE, int EPL>
+// Whether the event loop keeps the next tile's inputs in flight in registers
+// (two register sets used in turn).  Off where the second set would not fit
+// the register budget of two waves per SIMD.
+template <typename Tin, int EPL, int K0, int K1>
+constexpr bool prefetch_tiles()
+{
+    return EPL * (int)sizeof(Tin) <= 8;
+}
+
+// The event loop of one segment (events [ev0, ev1) of sample s).
+template <typename Tin, int PREC, int MODE, int EPL, int K0, int K1>
+__device__ __forceinline__ void run_segment(const KParams &kp, int s, const SegIO &io, const Seg &g,
+                                            int64_t ev0, int64_t ev1, uint32_t *myhist, WaveCounts &wc)
+{
+    const int64_t lane0 = (int64_t)EPL * threadIdx.x;
+    const int64_t step = (int64_t)EPL * blockDim.x;
+    if constexpr (prefetch_tiles<Tin, EPL, K0, K1>()) {
+        // tile t is evaluated while tile t + 1 loads into the other register set
+        Tin qa[EPL][4][4], qb[EPL][4][4];
+        int ta[EPL], tb[EPL];
+        int64_t t0 = ev0;
+        if (t0 < ev1) load_events<Tin, EPL>(io.ptr, io.tag, t0 + lane0, io.vec, ev1, qa, ta);
+        while (t0 < ev1) {
+            const int64_t t1 = t0 + step;
+            if (t1 < ev1) load_events<Tin, EPL>(io.ptr, io.tag, t1 + lane0, io.vec, ev1, qb, tb);
+            process_tile<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, qa, ta, t0 + lane0, ev1, myhist, wc);
+            if (t1 >= ev1) break;
+            const int64_t t2 = t1 + step;
+            if (t2 < ev1) load_events<Tin, EPL>(io.ptr, io.tag, t2 + lane0, io.vec, ev1, qa, ta);
+            process_tile<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, qb, tb, t1 + lane0, ev1, myhist, wc);
+            t0 = t2;
+        }
+    } else {
+        for (int64_t t0 = ev0; t0 < ev1; t0 += step) {
+            Tin q[EPL][4][4];
+            int tg[EPL];
+            load_events<Tin, EPL>(io.ptr, io.tag, t0 + lane0, io.vec, ev1, q, tg);
+            process_tile<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, q, tg, t0 + lane0, ev1, myhist, wc);
+        }
+    }
+}
+
+// The pass over samples [kp.sbeg, kp.send), all of binning scheme (K0, K1):
+// each workgroup takes a contiguous range of the virtual event space, splits
+// it at sample boundaries, counts into LDS and flushes every segment.
+template <typename Tin, int PREC, int MODE, int EPL, int K0, int K1>
 __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -592,19 +633,19 @@ __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
     const int wave = tid >> 6;
     uint32_t *myhist = hist + (wave % kp.lds_copies) * kp.hist_stride;
 
-    int64_t vbeg = (int64_t)blockIdx.x * kp.range;
-    const int64_t vend = vbeg + kp.range < kp.vtotal ? vbeg + kp.range : kp.vtotal;
+    int64_t vbeg = kp.vbeg + (int64_t)blockIdx.x * kp.range;
+    const int64_t vend = vbeg + kp.range < kp.vend ? vbeg + kp.range : kp.vend;
     if (vbeg >= vend) return;
-    int lo = 0, hi = kp.nsamples - 1;
+    int lo = kp.sbeg, hi = kp.send - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (kp.samples[mid].vstart <= vbeg) lo = mid;
         else hi = mid - 1;
     }
-    for (int s = lo; s < kp.nsamples && vbeg < vend; ++s) {
+    for (int s = lo; s < kp.send && vbeg < vend; ++s) {
         const KSample *S = kp.samples + s;
         const int64_t sv0 = S->vstart;
-        const int64_t sv1 = s + 1 < kp.nsamples ? kp.samples[s + 1].vstart : kp.vtotal;
+        const int64_t sv1 = s + 1 < kp.send ? kp.samples[s + 1].vstart : kp.vend;
         if (sv1 <= vbeg) continue;
         const int64_t segend = vend < sv1 ? vend : sv1;
         const int64_t n = S->n;
@@ -625,9 +666,6 @@ __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
         uint64_t *stats = S->stats;
         Seg g;
         g.sigma = S->sigma;
-        const int naxes = MODE == 0 ? S->naxes : 0;
-        const int kind0 = naxes > 0 ? S->kind[0] : AX_NONE;
-        const int kind1 = naxes > 1 ? S->kind[1] : AX_NONE;
         g.nb0 = S->nbins[0];
         g.nb1 = S->nbins[1];
         g.slots0 = S->slots[0];
@@ -636,8 +674,8 @@ __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
         g.glo1 = S->guess_lo[1];
         g.ginv0 = S->guess_inv[0];
         g.ginv1 = S->guess_inv[1];
-        const int nd0 = naxes > 0 ? edge_doubles(kind0, g.nb0) : 0;
-        const int nd1 = naxes > 1 ? edge_doubles(kind1, g.nb1) : 0;
+        const int nd0 = K0 != AX_NONE ? edge_doubles(K0, g.nb0) : 0;
+        const int nd1 = K1 != AX_NONE ? edge_doubles(K1, g.nb1) : 0;
         const int eoff0 = S->eoff[0], eoff1 = S->eoff[1];
         const int nrow = (S->nbtot + 1) * 4;
         g.e0 = ecache;
@@ -649,26 +687,7 @@ __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
         __syncthreads();
 
         WaveCounts wc = { 0, 0, 0, 0, 0, 0, 0, 0, 0, 0 };
-#define TP_SEG(A, B) run_segment<Tin, PREC, MODE, EPL, A, B>(kp, s, io, g, ev0, ev1, myhist, wc)
-        if constexpr (MODE == 1) {
-            TP_SEG(AX_NONE, AX_NONE);
-        } else {
-            switch (kind0 * 4 + kind1) {
-            case AX_ABSPHI * 4 + AX_NONE: TP_SEG(AX_ABSPHI, AX_NONE); break;
-            case AX_MASS * 4 + AX_NONE: TP_SEG(AX_MASS, AX_NONE); break;
-            case AX_ABSCOS * 4 + AX_NONE: TP_SEG(AX_ABSCOS, AX_NONE); break;
-            case AX_ABSPHI * 4 + AX_MASS: TP_SEG(AX_ABSPHI, AX_MASS); break;
-            case AX_ABSPHI * 4 + AX_ABSCOS: TP_SEG(AX_ABSPHI, AX_ABSCOS); break;
-            case AX_MASS * 4 + AX_ABSPHI: TP_SEG(AX_MASS, AX_ABSPHI); break;
-            case AX_MASS * 4 + AX_MASS: TP_SEG(AX_MASS, AX_MASS); break;
-            case AX_MASS * 4 + AX_ABSCOS: TP_SEG(AX_MASS, AX_ABSCOS); break;
-            case AX_ABSCOS * 4 + AX_ABSPHI: TP_SEG(AX_ABSCOS, AX_ABSPHI); break;
-            case AX_ABSCOS * 4 + AX_MASS: TP_SEG(AX_ABSCOS, AX_MASS); break;
-            case AX_ABSCOS * 4 + AX_ABSCOS: TP_SEG(AX_ABSCOS, AX_ABSCOS); break;
-            default: TP_SEG(AX_NONE, AX_NONE); break;
-            }
-        }
-#undef TP_SEG
+        run_segment<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, ev0, ev1, myhist, wc);
         if (lane == 0) {
             if (MODE == 0) {
                 atomicAdd(&myhist[0], wc.c0);
@@ -703,35 +722,74 @@ __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
 
 // ------------------------------------------------------------------ launchers
 namespace {
-template <typename T, int P, int M>
+template <typename T, int P, int M, int EPL, int K0, int K1>
+void launch_one(const KParams &kp, int grid, int block, size_t lds, hipStream_t st)
+{
+    // with a plane angle binned, the float32-sign variant is the float64 one
+    constexpr int PE = (K0 == AX_ABSPHI || K1 == AX_ABSPHI) ? 0 : P;
+    hipLaunchKernelGGL((tp_pass_kernel<T, PE, M, EPL, K0, K1>), dim3(grid), dim3(block), lds, st, kp);
+}
+
+template <typename T, int P, int M, int K0, int K1>
 void launch_epl(int epl, const KParams &kp, int grid, int block, size_t lds, hipStream_t st)
 {
     if constexpr (sizeof(T) == 4) {
         if (epl >= 4) {
-            hipLaunchKernelGGL((tp_pass_kernel<T, P, M, 4>), dim3(grid), dim3(block), lds, st, kp);
+            launch_one<T, P, M, 4, K0, K1>(kp, grid, block, lds, st);
             return;
         }
     }
-    if (epl >= 2) hipLaunchKernelGGL((tp_pass_kernel<T, P, M, 2>), dim3(grid), dim3(block), lds, st, kp);
-    else hipLaunchKernelGGL((tp_pass_kernel<T, P, M, 1>), dim3(grid), dim3(block), lds, st, kp);
+    if (epl >= 2) launch_one<T, P, M, 2, K0, K1>(kp, grid, block, lds, st);
+    else launch_one<T, P, M, 1, K0, K1>(kp, grid, block, lds, st);
+}
+
+template <typename T, int P, int M>
+bool launch_scheme(int k0, int k1, int epl, const KParams &kp, int grid, int block, size_t lds, hipStream_t st)
+{
+    if constexpr (M == 1) {
+        if (k0 != AX_NONE || k1 != AX_NONE) return false;
+        launch_epl<T, P, M, AX_NONE, AX_NONE>(epl, kp, grid, block, lds, st);
+        return true;
+    } else {
+#define TP_CASE(A, B)                                                          \
+    case A * 4 + B: launch_epl<T, P, M, A, B>(epl, kp, grid, block, lds, st); return true;
+        switch (k0 * 4 + k1) {
+            TP_CASE(AX_NONE, AX_NONE)
+            TP_CASE(AX_ABSPHI, AX_NONE)
+            TP_CASE(AX_MASS, AX_NONE)
+            TP_CASE(AX_ABSCOS, AX_NONE)
+            TP_CASE(AX_ABSPHI, AX_MASS)
+            TP_CASE(AX_ABSPHI, AX_ABSCOS)
+            TP_CASE(AX_MASS, AX_ABSPHI)
+            TP_CASE(AX_MASS, AX_MASS)
+            TP_CASE(AX_MASS, AX_ABSCOS)
+            TP_CASE(AX_ABSCOS, AX_ABSPHI)
+            TP_CASE(AX_ABSCOS, AX_MASS)
+            TP_CASE(AX_ABSCOS, AX_ABSCOS)
+        default: return false;
+        }
+#undef TP_CASE
+    }
 }
 }  // namespace
 
-hipError_t launch_pass(int dtype, int prec, int mode, int epl, const KParams &kp, int grid, int block,
-                       size_t lds, hipStream_t st)
+hipError_t launch_pass(int dtype, int prec, int mode, int epl, int k0, int k1, const KParams &kp, int grid,
+                       int block, size_t lds, hipStream_t st)
 {
+    bool ok;
     if (dtype == 0) {
         if (prec == 1) {
-            if (mode == 0) launch_epl<float, 1, 0>(epl, kp, grid, block, lds, st);
-            else launch_epl<float, 1, 1>(epl, kp, grid, block, lds, st);
+            ok = mode == 0 ? launch_scheme<float, 1, 0>(k0, k1, epl, kp, grid, block, lds, st)
+                           : launch_scheme<float, 1, 1>(k0, k1, epl, kp, grid, block, lds, st);
         } else {
-            if (mode == 0) launch_epl<float, 0, 0>(epl, kp, grid, block, lds, st);
-            else launch_epl<float, 0, 1>(epl, kp, grid, block, lds, st);
+            ok = mode == 0 ? launch_scheme<float, 0, 0>(k0, k1, epl, kp, grid, block, lds, st)
+                           : launch_scheme<float, 0, 1>(k0, k1, epl, kp, grid, block, lds, st);
         }
     } else {
-        if (mode == 0) launch_epl<double, 0, 0>(epl, kp, grid, block, lds, st);
-        else launch_epl<double, 0, 1>(epl, kp, grid, block, lds, st);
+        ok = mode == 0 ? launch_scheme<double, 0, 0>(k0, k1, epl, kp, grid, block, lds, st)
+                       : launch_scheme<double, 0, 1>(k0, k1, epl, kp, grid, block, lds, st);
     }
+    if (!ok) return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -222,3 +222,32 @@ def test_chunked_equals_whole(tp):
     c = [int(x) for x in u64(counts)]
     assert [c[4 * r:4 * r + 4] for r in range(bn.nrows)] == whole[0]
     assert [int(x) for x in u64(stats)][:4] == whole[1][:4]
+
+
+@pytest.mark.parametrize("dtype,k", [(torch.float64, -560), (torch.float64, 250),
+                                     (torch.float32, -80), (torch.float32, 80)])
+def test_scale_invariance(tp, dtype, k):
+    """Classes and |Phi|, |cos theta| bins are invariant under p -> 2^k p (mass bins
+    when their edges scale too).  At these scales products underflow or overflow
+    float64, so the fast bounds must defer and the later tiers decide."""
+    ch = synth.CHANNELS["Lb_pKpipi"]
+    s = synth.generate(ch, 2003, 70, dtype=dtype)
+    comps, tag = s.numpy()
+    f = 2.0 ** k
+    scaled = [[t * f for t in row] for row in s.comps]
+    for row, srow in zip(s.comps, scaled):
+        for t, st in zip(row, srow):
+            assert torch.equal(st / f, t), "scaling must be exact"
+    ss = synth.Sample(ch, scaled, s.tag)
+    mass = synth.lb_mass03_axis(ch)
+    for axes in ([synth.absphi_axis(12)], [synth.abscos_axis(0, 5), synth.absphi_axis(10)],
+                 [synth.absphi_axis(10), mass]):
+        want = oracle.run(comps, tag, ch.triple, ch.planes, axes)
+        sax = [synth.Axis(a.kind, a.edges * f, a.slots) if a.kind == synth.AXIS_MASS else a for a in axes]
+        precs = [tp.TP_PREC_F64] + ([tp.TP_PREC_F32_RECHECK] if dtype == torch.float32 else [])
+        for prec in precs:
+            counts, stats = gpu_bin(tp, ss, ch, sax, prec)
+            print(f"[scale] k={k} {dtype} prec={prec} stats={stats}", flush=True)
+            assert stats[6] == 0
+            assert counts == want["counts"]
+            assert stats[:4] == want["stats"]
