@@ -120,6 +120,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tuning", default=None,
                     help="fixed launch shape block,wg_per_cu,lds_copies,events_per_lane (skips the autotuner)")
+    ap.add_argument("--no-f64-path", action="store_true",
+                    help="skip the per-sample float64 comparison leg (profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -187,24 +189,28 @@ def main():
     tier2, tier3, unres = st[4] / reps, st[5] / reps, st[6] / reps
 
     # plain all-float64 single-sample path, same inputs (non-persistent per-sample launches)
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    f64_items = [(ds, ch, bn, *tpasym.new_counts(bn, dev)) for ds, ch, bn, _, _ in items]
-    for ds, ch, bn, c, s in f64_items:
-        tpasym.bin(ds, ch, bn, tpasym.TP_PREC_F64, c, s)
-    torch.cuda.synchronize()
-    f64_steps = max(3, args.steps // 4)
-    t0.record(stream)
-    for _ in range(f64_steps):
+    f64_leg = None
+    if not args.no_f64_path:
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        f64_items = [(ds, ch, bn, *tpasym.new_counts(bn, dev)) for ds, ch, bn, _, _ in items]
         for ds, ch, bn, c, s in f64_items:
             tpasym.bin(ds, ch, bn, tpasym.TP_PREC_F64, c, s)
-    t1.record(stream)
-    torch.cuda.synchronize()
-    f64_ms = t0.elapsed_time(t1) / f64_steps
-    # both paths must agree bit for bit
-    agree = all(np.array_equal(a[3].cpu().numpy().view(np.uint64) // reps,
-                               b[3].cpu().numpy().view(np.uint64) // (f64_steps + 1))
-                for a, b in zip(items, f64_items))
+        torch.cuda.synchronize()
+        f64_steps = max(3, args.steps // 4)
+        t0.record(stream)
+        for _ in range(f64_steps):
+            for ds, ch, bn, c, s in f64_items:
+                tpasym.bin(ds, ch, bn, tpasym.TP_PREC_F64, c, s)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        f64_ms = t0.elapsed_time(t1) / f64_steps
+        # both paths must agree bit for bit
+        agree = all(np.array_equal(a[3].cpu().numpy().view(np.uint64) // reps,
+                                   b[3].cpu().numpy().view(np.uint64) // (f64_steps + 1))
+                    for a, b in zip(items, f64_items))
+        f64_leg = {"value": nevents / (f64_ms / 1e3), "unit": "events/s", "ms_per_step": f64_ms,
+                   "counts_equal_fast_path": bool(agree)}
 
     wl = args.workload
     if args.scale != 1.0:
@@ -232,8 +238,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS if achieved else None,
                      "traffic": traffic,
                      "bytes_per_event": bpe, "kernel_ms": kern_ms, "kernel_launches": launches},
-        "fp64_single_sample": {"value": nevents / (f64_ms / 1e3), "unit": "events/s", "ms_per_step": f64_ms,
-                               "counts_equal_fast_path": bool(agree)},
+        "fp64_single_sample": f64_leg,
         "tiers": {"tier2_per_step": tier2, "tier3_per_step": tier3, "unresolved_per_step": unres},
         "paper_context": "energy test (different algorithm): 1e6 events, one permutation ~30 min on "
                          "NVIDIA M2070 / K40c (Sect. 6); no timing is given for the triple-product pass",

@@ -274,13 +274,28 @@ void fill_sample(KSample &k, const tp_events &ev, const tp_channel &ch, const tp
                  std::vector<double> &edges)
 {
     std::memset(&k, 0, sizeof k);
+    // Kernel order: kernel slot t holds channel slot planes[t ^ r].  The XOR
+    // relabelling t -> t ^ r is the identity or a product of two transpositions
+    // ((01)(23), (02)(13), (03)(12)): an even permutation that maps the plane
+    // pair {(0,1), (2,3)} onto itself with the orientation of both normals
+    // reversed together or swapped, so the triple-product sign and cos Phi are
+    // unchanged.  r moves the slot of the first |cos theta| axis to kernel
+    // slot 0, which the kernel then reads at a fixed position.
+    int r = 0;
+    if (bn)
+        for (int a = 0; a < bn->naxes; ++a)
+            if (bn->axis[a].kind == TP_AXIS_ABSCOS) {
+                for (int t = 0; t < 4; ++t)
+                    if (ch.planes[t] == bn->axis[a].slots) r = t;
+                break;
+            }
     int inv[4];
-    for (int t = 0; t < 4; ++t) inv[ch.planes[t]] = t;   // channel slot -> kernel slot
+    for (int t = 0; t < 4; ++t) inv[ch.planes[t ^ r]] = t;   // channel slot -> kernel slot
     bool vec = true;
     for (int t = 0; t < 4; ++t)
         for (int c = 0; c < 4; ++c) {
-            k.p[t * 4 + c] = ev.p[ch.planes[t]][c];
-            vec = vec && aligned16(ev.p[ch.planes[t]][c]);
+            k.p[t * 4 + c] = ev.p[ch.planes[t ^ r]][c];
+            vec = vec && aligned16(ev.p[ch.planes[t ^ r]][c]);
         }
     k.tag = ev.tag;
     vec = vec && ((reinterpret_cast<uintptr_t>(ev.tag) & 3u) == 0);
@@ -291,7 +306,7 @@ void fill_sample(KSample &k, const tp_events &ev, const tp_channel &ch, const tp
     k.cls_out = cls_out;
     k.ct_out = ct_out;
     // sigma: C_T^inv = det[p_D; p_A; p_B; p_C] = sgn(D,A,B,C) det[p0..p3]
-    //        det[kernel rows] = sgn(planes) det[p0..p3]
+    //        det[kernel rows] = sgn(planes) det[p0..p3] (the relabelling is even)
     int D = 0 + 1 + 2 + 3 - ch.triple[0] - ch.triple[1] - ch.triple[2];
     int dabc[4] = { D, ch.triple[0], ch.triple[1], ch.triple[2] };
     k.sigma = perm_sign(dabc, 4) * perm_sign(ch.planes, 4);
@@ -395,7 +410,8 @@ int build_plan(Device &d, const std::vector<Req> &rq, int mode, hipStream_t st, 
         Group &g = p->groups.back();
         g.send = sidx + 1;
         g.vend = v;
-        const int stride = (k.nbtot + 1) * 4 + NSTAT;
+        // LDS histogram copy: class-total row, bin rows, overflow row, statistics
+        const int stride = (k.nbtot + 2) * 4 + NSTAT;
         g.hist_stride = std::max(g.hist_stride, stride);
         int ed = 0;
         for (int a = 0; a < k.naxes; ++a) ed += edge_doubles(k.kind[a], k.nbins[a]);
@@ -484,7 +500,7 @@ int launch_plan(Device &d, const Plan &p, const tp_tuning &tu_in, int prec, int 
         int copies = tu.lds_copies;
         size_t hist_bytes = 0;
         for (;;) {
-            hist_bytes = ((size_t)copies * g.hist_stride * 4 + 15) & ~size_t(15);
+            hist_bytes = ((size_t)(8 + copies * g.hist_stride) * 4 + 15) & ~size_t(15);
             if (hist_bytes + (size_t)g.edge_doubles * 8 <= LDS_LIMIT || copies == 1) break;
             --copies;
         }
@@ -496,6 +512,8 @@ int launch_plan(Device &d, const Plan &p, const tp_tuning &tu_in, int prec, int 
         if (grid < 1) grid = 1;
         int64_t range = (nv + grid - 1) / grid;
         range = (range + tile - 1) / tile * tile;
+        // the kernel forms in-segment offsets in 32 bits: at most 2^26 events a workgroup
+        range = std::min<int64_t>(range, int64_t(1) << 26);
         grid = (nv + range - 1) / range;
         kp.sbeg = g.sbeg;
         kp.send = g.send;

@@ -159,6 +159,32 @@ __device__ __forceinline__ double ratio_eps(double v, double r, double rel, doub
     return fma(1.01, fma(dabs(v), rel + U64, fma(eY, r, 0.54 * eD * r * r)), 3.0 * U64);
 }
 
+// Counts over the inner edges e[1..n-1] (LDS) for the two ends of an
+// interval, in one pass: LE = true counts x <= e[k], LE = false counts
+// e[k] <= x.  A bin is certified when both ends give the same count (no edge
+// falls inside the interval).  Branch-free body, unrolled by four.
+template <bool LE>
+__device__ __forceinline__ void count_edges(double xa, double xb, const double *e, int n, int &ca, int &cb)
+{
+    int a = 0, b = 0;
+    int k = 1;
+    for (; k + 3 < n; k += 4) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double c = e[k + i];
+            a += LE ? (xa <= c) : (c <= xa);
+            b += LE ? (xb <= c) : (c <= xb);
+        }
+    }
+    for (; k < n; ++k) {
+        const double c = e[k];
+        a += LE ? (xa <= c) : (c <= xa);
+        b += LE ? (xb <= c) : (c <= xb);
+    }
+    ca = a;
+    cb = b;
+}
+
 // Plane angle between kernel planes (0,1) and (2,3) from the bivectors
 // B1 = p0^p1, B2 = p2^p3 (their minors m01, m23).  The covector C with
 // det[c; P; a; b] = c.C for every c is, in the M rest frame, (0, +-M (p*_a x p*_b)),
@@ -209,21 +235,18 @@ __device__ __forceinline__ int bin_absphi_bv(const double (&m01)[6], const doubl
     const double r = rsqrt_cert(D, rel, ok);
     const double v = -X * r;
     const double eps = ratio_eps(v, r, rel, eX, eD);
-    const double vhi = v + eps, vlo = v - eps;
-    int bin = 0;
-    for (int k = 1; k < n; ++k) {
-        const double c = edges[k];
-        const bool le = vhi <= c;
-        bin += le ? 1 : 0;
-        ok = ok && (le || vlo > c);
-    }
-    sure = sure && ok;
+    // bin = #{k : cos Phi <= c_k}: certified when vhi and vlo pass the same edges
+    int bin, blo;
+    count_edges<true>(v + eps, v - eps, edges, n, bin, blo);
+    sure = sure && ok && bin == blo;
     return bin;
 }
 
 // |cos theta| of kernel slot s against the M flight direction:
 // Nn = (P.p_s) E_P - M^2 E_s, A = G_ss, B = |P_lab|^2, |cos| = |Nn| / sqrt(A B).
 // edges 0 = e_0 < ... < e_n = 1; returns #{k in 1..n-1 : |cos| >= e_k}.
+// SLOT0: the slot is kernel slot 0 (the host relabels the slots so), else s.
+template <bool SLOT0>
 __device__ __forceinline__ int bin_abscos(const double x[4][4], const double w[4], double W,
                                           const double P[4], double M2, double eM, double kdot,
                                           int s, const double *edges, int n, bool &sure)
@@ -232,18 +255,20 @@ __device__ __forceinline__ int bin_abscos(const double x[4][4], const double w[4
     double ws = w[0];
 #pragma unroll
     for (int c = 0; c < 4; ++c) xs[c] = x[0][c];
-    if (s == 1) {
+    if (!SLOT0) {
+        if (s == 1) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) xs[c] = x[1][c];
-        ws = w[1];
-    } else if (s == 2) {
+            for (int c = 0; c < 4; ++c) xs[c] = x[1][c];
+            ws = w[1];
+        } else if (s == 2) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) xs[c] = x[2][c];
-        ws = w[2];
-    } else if (s == 3) {
+            for (int c = 0; c < 4; ++c) xs[c] = x[2][c];
+            ws = w[2];
+        } else if (s == 3) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) xs[c] = x[3][c];
-        ws = w[3];
+            for (int c = 0; c < 4; ++c) xs[c] = x[3][c];
+            ws = w[3];
+        }
     }
     const double u2 = 2.01 * U64;
     const double PPs = mink(P, xs);
@@ -269,15 +294,10 @@ __device__ __forceinline__ int bin_abscos(const double x[4][4], const double w[4
     const double r = rsqrt_cert(D, rel, ok);
     const double v = dabs(Nn) * r;
     const double eps = ratio_eps(v, r, rel, eNn, eD);
-    const double vhi = v + eps, vlo = v - eps;
-    int bin = 0;
-    for (int k = 1; k < n; ++k) {
-        const double e = edges[k];
-        const bool ge = vlo >= e;
-        bin += ge ? 1 : 0;
-        ok = ok && (ge || vhi < e);
-    }
-    sure = sure && ok;
+    // bin = #{k : |cos| >= e_k}: certified when vlo and vhi pass the same edges
+    int bin, bhi;
+    count_edges<false>(v - eps, v + eps, edges, n, bin, bhi);
+    sure = sure && ok && bin == bhi;
     return bin;
 }
 
@@ -286,51 +306,50 @@ __device__ __forceinline__ int bin_abscos(const double x[4][4], const double w[4
 __device__ __forceinline__ int bin_mass(const double x[4][4], const double w[4], int mask,
                                         const double *ed, int n, double glo, double ginv, bool &sure)
 {
-    double S[4] = { 0.0, 0.0, 0.0, 0.0 };
-    double WS = 0.0;
+    // sum of the slots in the mask with 0/1 weights: b x is exact, so every
+    // fused step rounds at most once and only where a slot is added
+    const double b0 = (mask & 1) ? 1.0 : 0.0, b1 = (mask & 2) ? 1.0 : 0.0;
+    const double b2 = (mask & 4) ? 1.0 : 0.0, b3 = (mask & 8) ? 1.0 : 0.0;
+    double S[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
-        if (mask & (1 << s)) {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) S[c] += x[s][c];
-            WS += w[s];
-        }
+    for (int c = 0; c < 4; ++c) S[c] = fma(b3, x[3][c], fma(b2, x[2][c], fma(b1, x[1][c], b0 * x[0][c])));
+    const double WS = fma(b3, w[3], fma(b2, w[2], fma(b1, w[1], b0 * w[0])));
     const double m2 = fma(-S[3], S[3], fma(-S[2], S[2], fma(-S[1], S[1], S[0] * S[0])));
     const double em = fma((12.4 * U64) * WS, WS, TINY);
     const double *sqlo = ed, *sqhi = ed + (n + 1);
     const double mlo = m2 - em, mhi = m2 + em;
-    // guess on a uniform grid in m, then certify against the two neighbouring edges
-    const float mg = sqrtf(fmaxf((float)m2, 0.0f));
-    const float t = (float)(((double)mg - glo) * ginv);
-    int j = 0;
-    if (t >= (float)(n - 1)) j = n - 1;
-    else if (t >= 0.0f) j = (int)t;
-    if (mlo >= sqhi[j] && (j == n - 1 ? mhi <= sqlo[n] : mhi < sqlo[j + 1])) return j;
+    // guess on a uniform grid in m (hardware square root: only a guess), then
+    // certify against the two neighbouring edges
+    const float mg = __builtin_amdgcn_sqrtf(fmaxf((float)m2, 0.0f));
+    const float t = (mg - (float)glo) * (float)ginv;
+    const int j = (int)fminf(fmaxf(t, 0.0f), (float)(n - 1));
+    // bin j when e_j^2 <= m^2 and m^2 < e_(j+1)^2 (<= for the last, closed bin)
+    const double ehi = sqlo[j + 1];
+    if (mlo >= sqhi[j] && (mhi < ehi || (j == n - 1 && mhi <= ehi))) return j;
     // full scan
     if (mhi < sqlo[0] || mlo > sqhi[n]) return -1;          // certainly outside
     if (!(mlo >= sqhi[0] && mhi <= sqlo[n])) {               // not certainly inside
         sure = false;
         return -1;
     }
-    int bin = 0;
-    bool dec = true;
+    // bin = #{k : m^2 >= e_k^2}: certified when mlo and mhi pass the same edges
+    int bin = 0, bhi = 0;
     for (int k = 1; k < n; ++k) {
-        const bool ge = mlo >= sqhi[k];
-        bin += ge ? 1 : 0;
-        dec = dec && (ge || mhi < sqlo[k]);
+        bin += mlo >= sqhi[k];
+        bhi += mhi >= sqlo[k];
     }
-    sure = sure && dec;
+    sure = sure && bin == bhi;
     return bin;
 }
 
 struct Seg {
-    int32_t sigma, nb0, nb1, slots0, slots1;
+    int32_t sigma, nb0, nb1, nbtot, slots0, slots1;
     double glo0, ginv0, glo1, ginv1;
     const double *e0, *e1;    // LDS edge data of each axis
 };
 
 // One axis of compile-time kind KIND: bin index, or -1 (out of range).
-template <int KIND, bool EXACTP>
+template <int KIND, bool EXACTP, bool SLOT0>
 __device__ __forceinline__ int axis_bin(const double (&x)[4][4], const double (&w)[4], double W,
                                         const double (&m01)[6], const double (&m23)[6],
                                         const double (&P)[4], double M2, double eM, int nb, int sl,
@@ -339,7 +358,7 @@ __device__ __forceinline__ int axis_bin(const double (&x)[4][4], const double (&
     constexpr double KDOT = EXACTP ? 3.02 : 4.02;
     if constexpr (KIND == AX_ABSPHI) return bin_absphi_bv(m01, m23, P, W, ed, nb, sure);
     else if constexpr (KIND == AX_MASS) return bin_mass(x, w, sl, ed, nb, glo, ginv, sure);
-    else return bin_abscos(x, w, W, P, M2, eM, KDOT, sl, ed, nb, sure);
+    else return bin_abscos<SLOT0>(x, w, W, P, M2, eM, KDOT, sl, ed, nb, sure);
 }
 
 // Whole event, with the binning scheme (K0, K1; AX_NONE = absent) fixed at
@@ -417,13 +436,14 @@ __device__ __forceinline__ EvOut eval_event(const Tin (&q)[4][4], int tag, const
         const double eM = (10.2 * U64) * W * W;
         bool bsure = true;
         o.why = 3;
-        const int j0 = axis_bin<K0, EXACTP>(x, w, W, m01, m23, P, M2, eM, g.nb0, g.slots0, g.e0, g.glo0, g.ginv0,
+        // the first |cos theta| axis reads kernel slot 0 (host relabelling)
+        const int j0 = axis_bin<K0, EXACTP, true>(x, w, W, m01, m23, P, M2, eM, g.nb0, g.slots0, g.e0, g.glo0, g.ginv0,
                                             bsure);
         bool oor = j0 < 0;
         int bin = j0 < 0 ? 0 : j0;
         if constexpr (K1 != AX_NONE) {
             if (bsure) o.why = 4;
-            const int j1 = axis_bin<K1, EXACTP>(x, w, W, m01, m23, P, M2, eM, g.nb1, g.slots1, g.e1, g.glo1,
+            const int j1 = axis_bin<K1, EXACTP, K0 != AX_ABSCOS>(x, w, W, m01, m23, P, M2, eM, g.nb1, g.slots1, g.e1, g.glo1,
                                                 g.ginv1, bsure);
             oor = oor || j1 < 0;
             bin = bin * g.nb1 + (j1 < 0 ? 0 : j1);
@@ -440,95 +460,116 @@ __device__ __forceinline__ uint32_t wave_count(bool p)
     return (uint32_t)__popcll(__ballot(p));
 }
 
+// Nontemporal load of element i (32-bit index) from a uniform base pointer:
+// the byte offset is formed in 32 bits so the load takes the scalar-base +
+// vector-offset addressing form.
 template <typename T>
-__device__ __forceinline__ T ldnt(const void *p, int64_t i)
+__device__ __forceinline__ T ldnt(const void *base, uint32_t i)
 {
     typedef const T __attribute__((address_space(1))) *gptr;
-    return __builtin_nontemporal_load((gptr)p + i);
+    const uint32_t byte = i * (uint32_t)sizeof(T);
+    return __builtin_nontemporal_load((gptr)((const char *)base + byte));
 }
 
-// Load EPL consecutive events (EPL = 1, 2 or 4 per lane) starting at ``base``
-// (a multiple of EPL) from the 16 component arrays and the tag array.
+// Load EPL consecutive events per lane, the lane's first at segment offset
+// ``off`` (a multiple of EPL), from the 16 component arrays and the tag array
+// (all advanced to the segment's first event).  ``full``: the whole tile lies
+// in the segment and the arrays are 16-byte aligned (uniform), so vector loads
+// apply; otherwise every offset is clamped to ``last`` (the segment's last
+// event), so every load stays in bounds and none is predicated.
+typedef const __attribute__((address_space(4))) KSample *ctab;
+
 template <typename Tin, int EPL>
-__device__ __forceinline__ void load_events(const void *const (&ptr)[16], const int8_t *tag, int64_t base,
-                                            bool vec_ok, int64_t n_valid, Tin (&q)[EPL][4][4], int (&tg)[EPL])
+__device__ __forceinline__ void load_events(ctab S, int64_t ev0, uint32_t off, uint32_t last, bool full,
+                                            Tin (&q)[EPL][4][4], int (&tg)[EPL])
 {
     constexpr int BYTES = EPL * (int)sizeof(Tin);
-    if (EPL > 1 && !(vec_ok && base + EPL <= n_valid)) {
+    // The table pointer is passed through an empty asm, so the compiler cannot
+    // hoist the scalar loads of the 16 array pointers out of the tile loop:
+    // they are re-read (scalar cache) per tile and occupy SGPRs only while the
+    // tile's loads issue.
+    asm volatile("" : "+s"(S));
+    const void *ptr[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) ptr[k] = static_cast<const Tin *>(S->p[k]) + ev0;
+    const int8_t *tag = S->tag + ev0;
+    if (EPL == 1 || !full) {
 #pragma unroll
         for (int e = 0; e < EPL; ++e) {
-            const int64_t i = base + e;
-            const bool in = i < n_valid;
+            const uint32_t o = off + e < last ? off + e : last;
 #pragma unroll
-            for (int k = 0; k < 16; ++k) q[e][k >> 2][k & 3] = in ? ldnt<Tin>(ptr[k], i) : (Tin)0;
-            tg[e] = in ? (int)ldnt<int8_t>(tag, i) : -1;
+            for (int k = 0; k < 16; ++k) q[e][k >> 2][k & 3] = ldnt<Tin>(ptr[k], o);
+            tg[e] = (int)ldnt<int8_t>(tag, o);
         }
         return;
     }
-    if constexpr (EPL == 1) {
-        const bool in = base < n_valid;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) q[0][k >> 2][k & 3] = in ? ldnt<Tin>(ptr[k], base) : (Tin)0;
-        tg[0] = in ? (int)ldnt<int8_t>(tag, base) : -1;
-    } else if constexpr (BYTES == 8) {
+    if constexpr (BYTES == 8) {
         typedef Tin v2 __attribute__((ext_vector_type(2)));
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            const v2 v = ldnt<v2>(ptr[k], base >> 1);
+            const v2 v = ldnt<v2>(ptr[k], off >> 1);
             q[0][k >> 2][k & 3] = v.x;
             q[1][k >> 2][k & 3] = v.y;
         }
-        const uint16_t t = ldnt<uint16_t>(tag, base >> 1);
+        const uint16_t t = ldnt<uint16_t>(tag, off >> 1);
         tg[0] = (int)(int8_t)(t & 0xff);
         tg[1] = (int)(int8_t)(t >> 8);
     } else if constexpr (EPL == 4 && sizeof(Tin) == 4) {
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            const f32x4 v = ldnt<f32x4>(ptr[k], base >> 2);
+            const f32x4 v = ldnt<f32x4>(ptr[k], off >> 2);
             q[0][k >> 2][k & 3] = v.x;
             q[1][k >> 2][k & 3] = v.y;
             q[2][k >> 2][k & 3] = v.z;
             q[3][k >> 2][k & 3] = v.w;
         }
-        const uint32_t t = ldnt<uint32_t>(tag, base >> 2);
+        const uint32_t t = ldnt<uint32_t>(tag, off >> 2);
 #pragma unroll
         for (int e = 0; e < 4; ++e) tg[e] = (int)(int8_t)(t >> (8 * e));
-    } else {   // EPL == 2, double: 16-byte loads
+    } else if constexpr (EPL == 2) {   // double: 16-byte loads
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            const f64x2 v = ldnt<f64x2>(ptr[k], base >> 1);
+            const f64x2 v = ldnt<f64x2>(ptr[k], off >> 1);
             q[0][k >> 2][k & 3] = v.x;
             q[1][k >> 2][k & 3] = v.y;
         }
-        const uint16_t t = ldnt<uint16_t>(tag, base >> 1);
+        const uint16_t t = ldnt<uint16_t>(tag, off >> 1);
         tg[0] = (int)(int8_t)(t & 0xff);
         tg[1] = (int)(int8_t)(t >> 8);
     }
 }
 
+// Class totals of a wave's events, for the schemes without bins (binned
+// schemes derive them from the histogram).
 struct WaveCounts {
-    uint32_t c0, c1, c2, c3, zero, inv, oor, t2, t3, un;
+    uint32_t c0, c1, c2, c3;
 };
 
 struct SegIO {
-    const void *ptr[16];
-    const int8_t *tag;
+    ctab S;                   // this sample's table entry
     int8_t *cls_out;
     double *ct_out;
     bool vec;
 };
 
-// One tile: EPL consecutive events per lane starting at ``base``.
+// LDS layout of one histogram copy: rows 0 .. nbtot + 1 of four class
+// counters (row 0 class totals, rows 1 .. nbtot the bins, row nbtot + 1 the
+// events outside every bin), then NSTAT statistics words.
+__device__ __forceinline__ int lds_stats(int nbtot) { return (nbtot + 2) * 4; }
+
+// One tile: EPL consecutive events per lane, the lane's first at segment
+// offset ``loc``; ``len`` events in the segment, which starts at event ev0.
 template <typename Tin, int PREC, int MODE, int EPL, int K0, int K1>
 __device__ __forceinline__ void process_tile(const KParams &kp, int s, const SegIO &io, const Seg &g,
-                                             const Tin (&q)[EPL][4][4], const int (&tg)[EPL], int64_t base,
-                                             int64_t ev1, uint32_t *myhist, WaveCounts &wc)
+                                             const Tin (&q)[EPL][4][4], const int (&tg)[EPL], uint32_t loc,
+                                             uint32_t len, int64_t ev0, uint32_t *myhist, int srow,
+                                             WaveCounts &wc)
 {
     constexpr bool BINNED = MODE == 0 && K0 != AX_NONE;
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
-        const int64_t i = base + e;
-        const bool in = i < ev1;
+        const uint32_t li = loc + e;
+        const bool in = li < len;
         EvOut o;
         if (in) {
             o = eval_event<Tin, PREC, K0, K1>(q[e], tg[e], g);
@@ -543,34 +584,42 @@ __device__ __forceinline__ void process_tile(const KParams &kp, int s, const Seg
         if (o.cls == CLS_DEFER) {
             const uint32_t slot = atomicAdd(kp.xcount, 1u);
             if (slot < kp.xcap) {
-                kp.xlist[slot] = ((uint64_t)o.why << 60) | ((uint64_t)s << 40) | (uint64_t)i;
+                kp.xlist[slot] = ((uint64_t)o.why << 60) | ((uint64_t)s << 40) | (uint64_t)(ev0 + li);
                 listed = true;
             } else {
                 unres = true;
             }
         }
         if (MODE == 1 && in) {
-            io.cls_out[i] = (int8_t)(unres ? CLS_UNRESOLVED : o.cls);
-            if (io.ct_out) io.ct_out[i] = o.ct;
+            io.cls_out[ev0 + li] = (int8_t)(unres ? CLS_UNRESOLVED : o.cls);
+            if (io.ct_out) io.ct_out[ev0 + li] = o.ct;
         }
         const bool classified = o.cls >= 0 && o.cls < 4;
-        if (BINNED && classified && o.bin >= 0) atomicAdd(&myhist[(1 + o.bin) * 4 + o.cls], 1u);
-        if (MODE == 0) {
+        if constexpr (BINNED) {
+            // out-of-range events go to the overflow row
+            const int row = 1 + (o.bin >= 0 ? o.bin : g.nbtot);
+            if (classified) atomicAdd(&myhist[row * 4 + o.cls], 1u);
+        } else if constexpr (MODE == 0) {
             wc.c0 += wave_count(o.cls == CLS_I);
             wc.c1 += wave_count(o.cls == CLS_II);
             wc.c2 += wave_count(o.cls == CLS_III);
             wc.c3 += wave_count(o.cls == CLS_IV);
         }
         // rare outcomes: one ballot decides whether the wave counts them
-        const bool oor = BINNED && classified && o.bin < 0;
-        const bool rare = (o.cls >= CLS_ZERO) || o.t2 || oor;
+        const bool rare = (o.cls >= CLS_ZERO) || o.t2;
         if (__ballot(rare)) {
-            wc.zero += wave_count(o.cls == CLS_ZERO);
-            wc.inv += wave_count(o.cls == CLS_INVALID);
-            wc.oor += wave_count(oor);
-            wc.t2 += wave_count(o.t2 != 0);
-            wc.t3 += wave_count(listed);
-            wc.un += wave_count(unres);
+            const uint32_t nz = wave_count(o.cls == CLS_ZERO);
+            const uint32_t ni = wave_count(o.cls == CLS_INVALID);
+            const uint32_t n2 = wave_count(o.t2 != 0);
+            const uint32_t n3 = wave_count(listed);
+            const uint32_t nu = wave_count(unres);
+            if ((threadIdx.x & 63) == 0) {
+                if (nz) atomicAdd(&myhist[srow + ST_ZERO], nz);
+                if (ni) atomicAdd(&myhist[srow + ST_INVALID], ni);
+                if (n2) atomicAdd(&myhist[srow + ST_TIER2], n2);
+                if (n3) atomicAdd(&myhist[srow + ST_TIER3], n3);
+                if (nu) atomicAdd(&myhist[srow + ST_UNRESOLVED], nu);
+            }
         }
     }
 }
@@ -584,35 +633,42 @@ constexpr bool prefetch_tiles()
     return EPL * (int)sizeof(Tin) <= 8;
 }
 
-// The event loop of one segment (events [ev0, ev1) of sample s).
+// The event loop of one segment: ``len`` events of sample s from event ev0,
+// addressed by 32-bit offsets (the host caps a workgroup's range).
 template <typename Tin, int PREC, int MODE, int EPL, int K0, int K1>
 __device__ __forceinline__ void run_segment(const KParams &kp, int s, const SegIO &io, const Seg &g,
-                                            int64_t ev0, int64_t ev1, uint32_t *myhist, WaveCounts &wc)
+                                            int64_t ev0, uint32_t len, uint32_t *myhist, int srow,
+                                            WaveCounts &wc)
 {
-    const int64_t lane0 = (int64_t)EPL * threadIdx.x;
-    const int64_t step = (int64_t)EPL * blockDim.x;
+    const uint32_t lane0 = (uint32_t)EPL * threadIdx.x;
+    const uint32_t step = (uint32_t)EPL * blockDim.x;
+    const uint32_t last = len - 1;
+    auto full = [&](uint32_t t) { return io.vec && t + step <= len; };
     if constexpr (prefetch_tiles<Tin, EPL, K0, K1>()) {
         // tile t is evaluated while tile t + 1 loads into the other register set
         Tin qa[EPL][4][4], qb[EPL][4][4];
         int ta[EPL], tb[EPL];
-        int64_t t0 = ev0;
-        if (t0 < ev1) load_events<Tin, EPL>(io.ptr, io.tag, t0 + lane0, io.vec, ev1, qa, ta);
-        while (t0 < ev1) {
-            const int64_t t1 = t0 + step;
-            if (t1 < ev1) load_events<Tin, EPL>(io.ptr, io.tag, t1 + lane0, io.vec, ev1, qb, tb);
-            process_tile<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, qa, ta, t0 + lane0, ev1, myhist, wc);
-            if (t1 >= ev1) break;
-            const int64_t t2 = t1 + step;
-            if (t2 < ev1) load_events<Tin, EPL>(io.ptr, io.tag, t2 + lane0, io.vec, ev1, qa, ta);
-            process_tile<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, qb, tb, t1 + lane0, ev1, myhist, wc);
+        uint32_t t0 = 0;
+        load_events<Tin, EPL>(io.S, ev0, t0 + lane0, last, full(t0), qa, ta);
+        while (t0 < len) {
+            const uint32_t t1 = t0 + step;
+            if (t1 < len) load_events<Tin, EPL>(io.S, ev0, t1 + lane0, last, full(t1), qb, tb);
+            process_tile<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, qa, ta, t0 + lane0, len, ev0, myhist, srow,
+                                                       wc);
+            if (t1 >= len) break;
+            const uint32_t t2 = t1 + step;
+            if (t2 < len) load_events<Tin, EPL>(io.S, ev0, t2 + lane0, last, full(t2), qa, ta);
+            process_tile<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, qb, tb, t1 + lane0, len, ev0, myhist, srow,
+                                                       wc);
             t0 = t2;
         }
     } else {
-        for (int64_t t0 = ev0; t0 < ev1; t0 += step) {
+        for (uint32_t t0 = 0; t0 < len; t0 += step) {
             Tin q[EPL][4][4];
             int tg[EPL];
-            load_events<Tin, EPL>(io.ptr, io.tag, t0 + lane0, io.vec, ev1, q, tg);
-            process_tile<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, q, tg, t0 + lane0, ev1, myhist, wc);
+            load_events<Tin, EPL>(io.S, ev0, t0 + lane0, last, full(t0), q, tg);
+            process_tile<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, q, tg, t0 + lane0, len, ev0, myhist, srow,
+                                                       wc);
         }
     }
 }
@@ -623,10 +679,12 @@ __device__ __forceinline__ void run_segment(const KParams &kp, int s, const SegI
 template <typename Tin, int PREC, int MODE, int EPL, int K0, int K1>
 __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
 {
+    constexpr bool BINNED = MODE == 0 && K0 != AX_NONE;
     extern __shared__ __align__(16) unsigned char smem[];
-    uint32_t *hist = reinterpret_cast<uint32_t *>(smem);
+    uint32_t *tot = reinterpret_cast<uint32_t *>(smem);          // 8 words: class totals, out of range
+    uint32_t *hist = tot + 8;
     const int hist_words = kp.lds_copies * kp.hist_stride;
-    double *ecache = reinterpret_cast<double *>(smem + ((hist_words * 4 + 15) & ~15));
+    double *ecache = reinterpret_cast<double *>(smem + (((8 + hist_words) * 4 + 15) & ~15));
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
     const int lane = tid & 63;
@@ -636,16 +694,19 @@ __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
     int64_t vbeg = kp.vbeg + (int64_t)blockIdx.x * kp.range;
     const int64_t vend = vbeg + kp.range < kp.vend ? vbeg + kp.range : kp.vend;
     if (vbeg >= vend) return;
+    // the sample table is read-only for the whole launch: read it through the
+    // constant address space, so its fields arrive by scalar loads
+    const ctab samples = (ctab)kp.samples;
     int lo = kp.sbeg, hi = kp.send - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (kp.samples[mid].vstart <= vbeg) lo = mid;
+        if (samples[mid].vstart <= vbeg) lo = mid;
         else hi = mid - 1;
     }
     for (int s = lo; s < kp.send && vbeg < vend; ++s) {
-        const KSample *S = kp.samples + s;
+        const ctab S = samples + s;
         const int64_t sv0 = S->vstart;
-        const int64_t sv1 = s + 1 < kp.send ? kp.samples[s + 1].vstart : kp.vend;
+        const int64_t sv1 = s + 1 < kp.send ? samples[s + 1].vstart : kp.vend;
         if (sv1 <= vbeg) continue;
         const int64_t segend = vend < sv1 ? vend : sv1;
         const int64_t n = S->n;
@@ -656,9 +717,7 @@ __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
 
         // everything the event loop needs, read once per segment
         SegIO io;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) io.ptr[k] = S->p[k];
-        io.tag = S->tag;
+        io.S = S;
         io.vec = S->vec != 0;
         io.cls_out = S->cls_out;
         io.ct_out = S->ct_out;
@@ -668,6 +727,7 @@ __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
         g.sigma = S->sigma;
         g.nb0 = S->nbins[0];
         g.nb1 = S->nbins[1];
+        g.nbtot = S->nbtot;
         g.slots0 = S->slots[0];
         g.slots1 = S->slots[1];
         g.glo0 = S->guess_lo[0];
@@ -677,41 +737,46 @@ __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
         const int nd0 = K0 != AX_NONE ? edge_doubles(K0, g.nb0) : 0;
         const int nd1 = K1 != AX_NONE ? edge_doubles(K1, g.nb1) : 0;
         const int eoff0 = S->eoff[0], eoff1 = S->eoff[1];
-        const int nrow = (S->nbtot + 1) * 4;
+        const int nrow = (g.nbtot + 1) * 4;      // counters of the output layout
+        const int srow = lds_stats(g.nbtot);
         g.e0 = ecache;
         g.e1 = ecache + nd0;
-        const int ncnt = nrow + NSTAT;
-        for (int i = tid; i < hist_words; i += nthr) hist[i] = 0;
+        for (int i = tid; i < 8 + hist_words; i += nthr) tot[i] = 0;   // tot and hist are contiguous
         for (int i = tid; i < nd0; i += nthr) ecache[i] = kp.edges[eoff0 + i];
         for (int i = tid; i < nd1; i += nthr) ecache[nd0 + i] = kp.edges[eoff1 + i];
         __syncthreads();
 
-        WaveCounts wc = { 0, 0, 0, 0, 0, 0, 0, 0, 0, 0 };
-        run_segment<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, ev0, ev1, myhist, wc);
-        if (lane == 0) {
-            if (MODE == 0) {
-                atomicAdd(&myhist[0], wc.c0);
-                atomicAdd(&myhist[1], wc.c1);
-                atomicAdd(&myhist[2], wc.c2);
-                atomicAdd(&myhist[3], wc.c3);
-            }
-            atomicAdd(&myhist[nrow + ST_ZERO], wc.zero);
-            atomicAdd(&myhist[nrow + ST_INVALID], wc.inv);
-            atomicAdd(&myhist[nrow + ST_OOR], wc.oor);
-            atomicAdd(&myhist[nrow + ST_TIER2], wc.t2);
-            atomicAdd(&myhist[nrow + ST_TIER3], wc.t3);
-            atomicAdd(&myhist[nrow + ST_UNRESOLVED], wc.un);
+        WaveCounts wc = { 0, 0, 0, 0 };
+        run_segment<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, ev0, (uint32_t)(ev1 - ev0), myhist, srow, wc);
+        if (!BINNED && MODE == 0 && lane == 0) {
+            atomicAdd(&myhist[0], wc.c0);
+            atomicAdd(&myhist[1], wc.c1);
+            atomicAdd(&myhist[2], wc.c2);
+            atomicAdd(&myhist[3], wc.c3);
         }
         __syncthreads();
-        for (int i = tid; i < ncnt; i += nthr) {
+        // fold the copies; bin rows also feed the class totals, the overflow
+        // row the totals and the out-of-range count
+        for (int i = tid; i < srow + NSTAT; i += nthr) {
             uint32_t v = 0;
             for (int k = 0; k < kp.lds_copies; ++k) v += hist[k * kp.hist_stride + i];
-            if (i < nrow) {
-                if (v && counts) atomicAdd((unsigned long long *)(counts + i), (unsigned long long)v);
-            } else if (i - nrow == ST_EVENTS) {
+            if (i < srow) {
+                if (BINNED && i >= 4 && v) atomicAdd(&tot[i & 3], v);
+                if (BINNED && i >= nrow && v) atomicAdd(&tot[4], v);
+                if (i < nrow && v && counts && (!BINNED || i >= 4))
+                    atomicAdd((unsigned long long *)(counts + i), (unsigned long long)v);
+            } else if (i - srow == ST_EVENTS) {
                 atomicAdd((unsigned long long *)(stats + ST_EVENTS), (unsigned long long)(ev1 - ev0));
             } else if (v) {
-                atomicAdd((unsigned long long *)(stats + (i - nrow)), (unsigned long long)v);
+                atomicAdd((unsigned long long *)(stats + (i - srow)), (unsigned long long)v);
+            }
+        }
+        if (BINNED) {
+            __syncthreads();
+            if (tid < 4) {
+                if (tot[tid] && counts) atomicAdd((unsigned long long *)(counts + tid), (unsigned long long)tot[tid]);
+            } else if (tid == 4) {
+                if (tot[4]) atomicAdd((unsigned long long *)(stats + ST_OOR), (unsigned long long)tot[4]);
             }
         }
         __syncthreads();
