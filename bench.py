@@ -147,12 +147,16 @@ def main():
     stream = torch.cuda.current_stream()
 
     tuning = None
+    tuning_desc = "library defaults"
     if args.tuning:
         tuning = tpasym.Tuning(*[int(v) for v in args.tuning.split(",")])
+        tuning_desc = tuning.as_dict()
     elif not args.no_autotune:
         t0 = time.time()
-        tuning = batch.autotune(prec)
-        log(f"autotune: {tuning.as_dict()} in {time.time() - t0:.1f}s")
+        largest = batch.autotune(prec)
+        # runs without an explicit shape take each scheme group's tuned shape
+        tuning_desc = {"per_scheme_autotuned": True, "largest_group": largest.as_dict()}
+        log(f"autotune: per scheme group, largest group {largest.as_dict()} in {time.time() - t0:.1f}s")
     graph = not args.no_graph
     for _ in range(args.warmup):
         batch.run(prec, tuning, graph)
@@ -233,7 +237,7 @@ def main():
         "config": {"workload": wl, "samples": len(samples), "events": nevents,
                    "storage": "f64" if f64_store else "f32",
                    "path": ("persistent batched pass, HIP graph" if graph else "persistent batched pass"),
-                   "precision": args.precision, "tuning": tuning.as_dict() if tuning else None},
+                   "precision": args.precision, "tuning": tuning_desc},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None,
                      "traffic": traffic,

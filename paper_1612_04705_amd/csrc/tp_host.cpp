@@ -469,14 +469,13 @@ void defaults(Device &d, tp_tuning &t, int64_t vtotal)
     (void)vtotal;
 }
 
-int launch_plan(Device &d, const Plan &p, const tp_tuning &tu_in, int prec, int mode, const Workspace &ws,
-                hipStream_t st)
+// Launch the plan's pass kernels (one per scheme group, each with its own
+// launch shape gtu[g]; only the group ``only`` when it is >= 0), then the
+// exact tier over the shared deferral list.
+int launch_plan(Device &d, const Plan &p, const std::vector<tp_tuning> &gtu, int prec, int mode,
+                const Workspace &ws, hipStream_t st, int only = -1)
 {
-    tp_tuning tu = tu_in;
-    defaults(d, tu, p.vtotal);
     if (p.vtotal == 0) return TP_OK;
-    const int epl = p.dtype == TP_F32 ? tu.unroll : std::min(tu.unroll, 2);
-    const int64_t tile = (int64_t)epl * tu.block;
     const bool timed = g_timing.on && !g_timing.ring.empty();
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
@@ -494,9 +493,15 @@ int launch_plan(Device &d, const Plan &p, const tp_tuning &tu_in, int prec, int 
     kp.xdone = ws.xdone;
     kp.xcap = XCAP;
     kp.mode = mode;
-    for (const Group &g : p.groups) {
+    for (size_t gi = 0; gi < p.groups.size(); ++gi) {
+        if (only >= 0 && (size_t)only != gi) continue;
+        const Group &g = p.groups[gi];
         const int64_t nv = g.vend - g.vbeg;
         if (nv <= 0) continue;
+        tp_tuning tu = gtu[gi];
+        defaults(d, tu, nv);
+        const int epl = p.dtype == TP_F32 ? tu.unroll : std::min(tu.unroll, 2);
+        const int64_t tile = (int64_t)epl * tu.block;
         int copies = tu.lds_copies;
         size_t hist_bytes = 0;
         for (;;) {
@@ -610,6 +615,41 @@ void save_tune_file(const Device &d)
     std::fclose(f);
 }
 
+// Tuning-cache key of one scheme group: storage, precision, binning kinds,
+// size class and histogram size.
+std::string group_key(const Plan &p, const Group &g, int prec)
+{
+    int nb = 0;
+    while ((int64_t(1) << nb) < g.vend - g.vbeg) ++nb;
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "g_d%d_p%d_k%d%d_n2^%d_h%d", p.dtype, prec, g.k0, g.k1, nb, g.hist_stride);
+    return buf;
+}
+
+// Launch shape of every group: the explicit tuning, else the group's tuned
+// entry, else the whole request's, else defaults.
+std::vector<tp_tuning> resolve_tunings(Device &d, const Plan &p, const std::vector<Req> &rq, int prec,
+                                       const tp_tuning *tuning)
+{
+    std::vector<tp_tuning> out(p.groups.size());
+    tp_tuning whole;
+    std::memset(&whole, 0, sizeof whole);
+    if (!tuning) {
+        auto it = d.tuned.find(tune_key(rq, prec));
+        if (it != d.tuned.end()) whole = it->second;
+    }
+    for (size_t g = 0; g < p.groups.size(); ++g) {
+        tp_tuning t = tuning ? *tuning : whole;
+        if (!tuning) {
+            auto it = d.tuned.find(group_key(p, p.groups[g], prec));
+            if (it != d.tuned.end()) t = it->second;
+        }
+        defaults(d, t, 0);
+        out[g] = t;
+    }
+    return out;
+}
+
 int current_device(int &id)
 {
     TP_HIP(hipGetDevice(&id));
@@ -624,21 +664,13 @@ int run(const std::vector<Req> &rq, int prec, int mode, const tp_tuning *tuning,
     std::lock_guard<std::mutex> lk(g_mu);
     Device &d = device(dev);
     load_tune_file(d);
-    tp_tuning tu;
-    std::memset(&tu, 0, sizeof tu);
-    if (tuning) {
-        tu = *tuning;
-    } else {
-        auto it = d.tuned.find(tune_key(rq, prec));
-        if (it != d.tuned.end()) tu = it->second;
-    }
-    defaults(d, tu, 0);
     Plan *p = nullptr;
     rc = build_plan(d, rq, mode, st, p);
     if (rc) return rc;
+    const std::vector<tp_tuning> gtu = resolve_tunings(d, *p, rq, prec, tuning);
     if (flags & TP_BATCH_GRAPH) {
         uint64_t gk = plan_key(rq, mode);
-        gk = fnv(&tu, sizeof tu, gk);
+        if (!gtu.empty()) gk = fnv(gtu.data(), gtu.size() * sizeof(tp_tuning), gk);
         gk = fnv(&prec, sizeof prec, gk);
         auto it = d.graphs.find(gk);
         if (it == d.graphs.end()) {
@@ -652,7 +684,7 @@ int run(const std::vector<Req> &rq, int prec, int mode, const tp_tuning *tuning,
             const bool was_on = g_timing.on;
             g_timing.on = false;
             TP_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-            rc = launch_plan(d, *p, tu, prec, mode, ge.ws, cap);
+            rc = launch_plan(d, *p, gtu, prec, mode, ge.ws, cap);
             hipGraph_t g = nullptr;
             hipError_t ee = hipStreamEndCapture(cap, &g);
             g_timing.on = was_on;
@@ -676,7 +708,7 @@ int run(const std::vector<Req> &rq, int prec, int mode, const tp_tuning *tuning,
     Workspace ws;
     rc = get_workspace(d, st, ws);
     if (rc) return rc;
-    return launch_plan(d, *p, tu, prec, mode, ws, st);
+    return launch_plan(d, *p, gtu, prec, mode, ws, st);
 }
 
 // exact ratio num/den of integers, rounded (long double division, then to double)
@@ -866,38 +898,64 @@ int tp_autotune(const tp_sample *samples, int32_t nsamples, int32_t precision, v
     hipEvent_t a, b;
     TP_HIP(hipEventCreate(&a));
     TP_HIP(hipEventCreate(&b));
-    float best_ms = 1e30f;
-    tp_tuning bt = cand[0];
+    std::lock_guard<std::mutex> lk(g_mu);
+    Device &d = device(dev);
+    load_tune_file(d);
     const bool was_on = g_timing.on;
     g_timing.on = false;
-    for (const tp_tuning &t : cand) {
-        rc = run(rq, precision, 0, &t, 0, st);   // warm-up (and plan build)
-        if (rc) break;
-        TP_HIP(hipEventRecord(a, st));
-        for (int r = 0; r < 3; ++r) {
-            rc = run(rq, precision, 0, &t, 0, st);
+    Plan *p = nullptr;
+    Workspace ws;
+    rc = build_plan(d, rq, 0, st, p);
+    if (!rc) rc = get_workspace(d, st, ws);
+    // each scheme group is tuned on its own launches
+    tp_tuning overall = cand[0];
+    int64_t largest = -1;
+    for (size_t g = 0; g < (p ? p->groups.size() : 0) && !rc; ++g) {
+        float best_ms = 1e30f;
+        tp_tuning bt = cand[0];
+        for (const tp_tuning &t : cand) {
+            const std::vector<tp_tuning> gtu(p->groups.size(), t);
+            rc = launch_plan(d, *p, gtu, precision, 0, ws, st, (int)g);   // warm-up
             if (rc) break;
+            // best of two trials of three launches each
+            float ms = 1e30f;
+            for (int trial = 0; trial < 2 && !rc; ++trial) {
+                TP_HIP(hipEventRecord(a, st));
+                for (int r = 0; r < 3 && !rc; ++r) rc = launch_plan(d, *p, gtu, precision, 0, ws, st, (int)g);
+                TP_HIP(hipEventRecord(b, st));
+                TP_HIP(hipEventSynchronize(b));
+                float m = 0;
+                TP_HIP(hipEventElapsedTime(&m, a, b));
+                ms = std::min(ms, m);
+            }
+            if (rc) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                bt = t;
+            }
         }
-        TP_HIP(hipEventRecord(b, st));
-        TP_HIP(hipEventSynchronize(b));
-        float ms = 0;
-        TP_HIP(hipEventElapsedTime(&ms, a, b));
-        if (ms < best_ms) {
-            best_ms = ms;
-            bt = t;
+        d.tuned[group_key(*p, p->groups[g], precision)] = bt;
+        static const bool debug = std::getenv("TP_DEBUG") != nullptr;
+        if (debug)
+            std::fprintf(stderr, "tp_debug: autotune group %zu (kinds %d,%d, %lld events): block %d wg/cu %d copies %d "
+                         "epl %d, %.4f ms per launch\n", g, p->groups[g].k0, p->groups[g].k1,
+                         (long long)(p->groups[g].vend - p->groups[g].vbeg), bt.block, bt.wg_per_cu, bt.lds_copies,
+                         bt.unroll, best_ms / 3);
+        const int64_t nv = p->groups[g].vend - p->groups[g].vbeg;
+        if (nv > largest) {
+            largest = nv;
+            overall = bt;
         }
     }
     g_timing.on = was_on;
     hipEventDestroy(a);
     hipEventDestroy(b);
     if (rc) return rc;
-    *best = bt;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        Device &d = device(dev);
-        d.tuned[tune_key(rq, precision)] = bt;
-        save_tune_file(d);
-    }
+    // the whole request's entry (for callers that pass it explicitly): the
+    // largest group's shape
+    *best = overall;
+    d.tuned[tune_key(rq, precision)] = overall;
+    save_tune_file(d);
     return TP_OK;
 }
 

@@ -471,43 +471,45 @@ __device__ __forceinline__ T ldnt(const void *base, uint32_t i)
     return __builtin_nontemporal_load((gptr)((const char *)base + byte));
 }
 
-// Load EPL consecutive events per lane, the lane's first at segment offset
-// ``off`` (a multiple of EPL), from the 16 component arrays and the tag array
-// (all advanced to the segment's first event).  ``full``: the whole tile lies
-// in the segment and the arrays are 16-byte aligned (uniform), so vector loads
-// apply; otherwise every offset is clamped to ``last`` (the segment's last
-// event), so every load stays in bounds and none is predicated.
 typedef const __attribute__((address_space(4))) KSample *ctab;
 
+// Load EPL consecutive events per lane, the lane's first at segment offset
+// ``off``, from the 16 component arrays and the tag array.  Every offset is
+// clamped to ``last`` (the segment's last event), so every load stays in
+// bounds and none is predicated.
 template <typename Tin, int EPL>
-__device__ __forceinline__ void load_events(ctab S, int64_t ev0, uint32_t off, uint32_t last, bool full,
+__device__ __forceinline__ void load_scalar(ctab S, int64_t ev0, uint32_t off, uint32_t last,
                                             Tin (&q)[EPL][4][4], int (&tg)[EPL])
 {
-    constexpr int BYTES = EPL * (int)sizeof(Tin);
     // The table pointer is passed through an empty asm, so the compiler cannot
     // hoist the scalar loads of the 16 array pointers out of the tile loop:
     // they are re-read (scalar cache) per tile and occupy SGPRs only while the
     // tile's loads issue.
     asm volatile("" : "+s"(S));
-    const void *ptr[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) ptr[k] = static_cast<const Tin *>(S->p[k]) + ev0;
     const int8_t *tag = S->tag + ev0;
-    if (EPL == 1 || !full) {
 #pragma unroll
-        for (int e = 0; e < EPL; ++e) {
-            const uint32_t o = off + e < last ? off + e : last;
+    for (int e = 0; e < EPL; ++e) {
+        const uint32_t o = off + e < last ? off + e : last;
 #pragma unroll
-            for (int k = 0; k < 16; ++k) q[e][k >> 2][k & 3] = ldnt<Tin>(ptr[k], o);
-            tg[e] = (int)ldnt<int8_t>(tag, o);
-        }
-        return;
+        for (int k = 0; k < 16; ++k) q[e][k >> 2][k & 3] = ldnt<Tin>(static_cast<const Tin *>(S->p[k]) + ev0, o);
+        tg[e] = (int)ldnt<int8_t>(tag, o);
     }
+}
+
+// The same for a tile lying wholly inside the segment, with 8- or 16-byte
+// vector loads (arrays 16-byte aligned, ``off`` a multiple of EPL).
+template <typename Tin, int EPL>
+__device__ __forceinline__ void load_vector(ctab S, int64_t ev0, uint32_t off, Tin (&q)[EPL][4][4],
+                                            int (&tg)[EPL])
+{
+    constexpr int BYTES = EPL * (int)sizeof(Tin);
+    asm volatile("" : "+s"(S));
+    const int8_t *tag = S->tag + ev0;
     if constexpr (BYTES == 8) {
         typedef Tin v2 __attribute__((ext_vector_type(2)));
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            const v2 v = ldnt<v2>(ptr[k], off >> 1);
+            const v2 v = ldnt<v2>(static_cast<const Tin *>(S->p[k]) + ev0, off >> 1);
             q[0][k >> 2][k & 3] = v.x;
             q[1][k >> 2][k & 3] = v.y;
         }
@@ -517,7 +519,7 @@ __device__ __forceinline__ void load_events(ctab S, int64_t ev0, uint32_t off, u
     } else if constexpr (EPL == 4 && sizeof(Tin) == 4) {
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            const f32x4 v = ldnt<f32x4>(ptr[k], off >> 2);
+            const f32x4 v = ldnt<f32x4>(static_cast<const Tin *>(S->p[k]) + ev0, off >> 2);
             q[0][k >> 2][k & 3] = v.x;
             q[1][k >> 2][k & 3] = v.y;
             q[2][k >> 2][k & 3] = v.z;
@@ -529,7 +531,7 @@ __device__ __forceinline__ void load_events(ctab S, int64_t ev0, uint32_t off, u
     } else if constexpr (EPL == 2) {   // double: 16-byte loads
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            const f64x2 v = ldnt<f64x2>(ptr[k], off >> 1);
+            const f64x2 v = ldnt<f64x2>(static_cast<const Tin *>(S->p[k]) + ev0, off >> 1);
             q[0][k >> 2][k & 3] = v.x;
             q[1][k >> 2][k & 3] = v.y;
         }
@@ -643,33 +645,62 @@ __device__ __forceinline__ void run_segment(const KParams &kp, int s, const SegI
     const uint32_t lane0 = (uint32_t)EPL * threadIdx.x;
     const uint32_t step = (uint32_t)EPL * blockDim.x;
     const uint32_t last = len - 1;
-    auto full = [&](uint32_t t) { return io.vec && t + step <= len; };
-    if constexpr (prefetch_tiles<Tin, EPL, K0, K1>()) {
-        // tile t is evaluated while tile t + 1 loads into the other register set
-        Tin qa[EPL][4][4], qb[EPL][4][4];
-        int ta[EPL], tb[EPL];
-        uint32_t t0 = 0;
-        load_events<Tin, EPL>(io.S, ev0, t0 + lane0, last, full(t0), qa, ta);
-        while (t0 < len) {
+    constexpr bool PF = prefetch_tiles<Tin, EPL, K0, K1>();
+    if constexpr (EPL == 1) {
+        // every tile takes the same (clamped) loads; tile t is evaluated while
+        // tile t + 1 loads into the other register set.  The loads issue
+        // unconditionally (past the end they re-read the last event), so no
+        // branch merges ahead of an evaluation and its wait covers only the
+        // tile being evaluated.
+        Tin qa[1][4][4], qb[1][4][4];
+        int ta[1], tb[1];
+        load_scalar<Tin, 1>(io.S, ev0, lane0, last, qa, ta);
+        for (uint32_t t0 = 0; t0 < len; t0 += 2 * step) {
             const uint32_t t1 = t0 + step;
-            if (t1 < len) load_events<Tin, EPL>(io.S, ev0, t1 + lane0, last, full(t1), qb, tb);
-            process_tile<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, qa, ta, t0 + lane0, len, ev0, myhist, srow,
-                                                       wc);
+            load_scalar<Tin, 1>(io.S, ev0, t1 + lane0, last, qb, tb);
+            process_tile<Tin, PREC, MODE, 1, K0, K1>(kp, s, io, g, qa, ta, t0 + lane0, len, ev0, myhist, srow, wc);
             if (t1 >= len) break;
-            const uint32_t t2 = t1 + step;
-            if (t2 < len) load_events<Tin, EPL>(io.S, ev0, t2 + lane0, last, full(t2), qa, ta);
-            process_tile<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, qb, tb, t1 + lane0, len, ev0, myhist, srow,
-                                                       wc);
-            t0 = t2;
+            load_scalar<Tin, 1>(io.S, ev0, t1 + step + lane0, last, qa, ta);
+            process_tile<Tin, PREC, MODE, 1, K0, K1>(kp, s, io, g, qb, tb, t1 + lane0, len, ev0, myhist, srow, wc);
+        }
+        return;
+    }
+    // EPL > 1: tiles wholly inside the segment take vector loads (aligned
+    // arrays), the partial tail tile (or everything, unaligned) scalar ones
+    const uint32_t nfull = io.vec ? len / step : 0;
+    if constexpr (PF) {
+        if (nfull > 0) {
+            // ping-pong as above; the next-tile index is clamped to the last
+            // full tile, so the vector loads never leave the segment
+            Tin qa[EPL][4][4], qb[EPL][4][4];
+            int ta[EPL], tb[EPL];
+            load_vector<Tin, EPL>(io.S, ev0, lane0, qa, ta);
+            for (uint32_t t = 0; t < nfull; t += 2) {
+                const uint32_t n1 = t + 1 < nfull ? t + 1 : nfull - 1;
+                load_vector<Tin, EPL>(io.S, ev0, n1 * step + lane0, qb, tb);
+                process_tile<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, qa, ta, t * step + lane0, len, ev0, myhist,
+                                                           srow, wc);
+                if (t + 1 >= nfull) break;
+                const uint32_t n2 = t + 2 < nfull ? t + 2 : nfull - 1;
+                load_vector<Tin, EPL>(io.S, ev0, n2 * step + lane0, qa, ta);
+                process_tile<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, qb, tb, (t + 1) * step + lane0, len, ev0,
+                                                           myhist, srow, wc);
+            }
         }
     } else {
-        for (uint32_t t0 = 0; t0 < len; t0 += step) {
+        for (uint32_t t = 0; t < nfull; ++t) {
             Tin q[EPL][4][4];
             int tg[EPL];
-            load_events<Tin, EPL>(io.S, ev0, t0 + lane0, last, full(t0), q, tg);
-            process_tile<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, q, tg, t0 + lane0, len, ev0, myhist, srow,
+            load_vector<Tin, EPL>(io.S, ev0, t * step + lane0, q, tg);
+            process_tile<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, q, tg, t * step + lane0, len, ev0, myhist, srow,
                                                        wc);
         }
+    }
+    for (uint32_t t0 = nfull * step; t0 < len; t0 += step) {
+        Tin q[EPL][4][4];
+        int tg[EPL];
+        load_scalar<Tin, EPL>(io.S, ev0, t0 + lane0, last, q, tg);
+        process_tile<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, q, tg, t0 + lane0, len, ev0, myhist, srow, wc);
     }
 }
 

@@ -81,6 +81,7 @@ def test_batch_workload_shape(tp):
         items.append((ds, tp.channel(spec.channel.triple, spec.channel.planes), bn, counts, stats))
     b = tp.Batch(items)
     for prec in (tp.TP_PREC_F32_RECHECK, tp.TP_PREC_F64):
+        b.autotune(prec)      # later runs without a shape take the per-scheme tuned ones
         for graph, reps in ((False, 1), (True, 3)):
             for it in items:
                 it[3].zero_()
