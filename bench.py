@@ -179,11 +179,12 @@ def main():
     log(f"{args.steps} steps: {ms_per_step:.4f} ms/step, kernel {kern_ms:.4f} ms over {launches} launches")
 
     if args.copy_calib:
-        # an elementwise kernel (not a DMA copy): reads 1 GiB, writes 1 GiB
-        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        # HBM counter calibration: an elementwise kernel no other step launches
+        # (not a DMA copy), reading 1 GiB and writing 1 GiB
+        src = torch.empty(1 << 28, dtype=torch.int32, device=dev).fill_(7)
         dst = torch.empty_like(src)
         for _ in range(2):
-            torch.mul(src, 2.0, out=dst)
+            torch.bitwise_not(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
 

@@ -20,7 +20,7 @@ struct KSample {
     const void *p[16];        // [kslot * 4 + c]
     const int8_t *tag;
     int64_t n;
-    int64_t vstart;           // start in the virtual event space (multiple of 4)
+    int64_t vstart;           // start in the virtual event space (multiple of 256)
     uint64_t *counts;         // [(nbtot + 1) * 4]
     uint64_t *stats;          // [NSTAT]
     int8_t *cls_out;          // optional per-event class (tp_compute)
@@ -47,7 +47,7 @@ struct KParams {
     int32_t hist_stride;      // uint32 counters per LDS copy
     int32_t edge_doubles;     // doubles of edge data cached in LDS per segment (max over samples)
     int32_t mode;             // 0 = counts, 1 = per-event outputs
-    int64_t range;            // virtual events per workgroup (multiple of 4)
+    int64_t range;            // virtual events per workgroup (multiple of the tile, >= 256)
     int64_t vbeg, vend;       // virtual event range of this launch
     const double *edges;      // edge table
     uint64_t *xlist;          // deferred events: (stage << 60) | (sample << 40) | event
