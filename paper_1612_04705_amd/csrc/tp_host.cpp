@@ -968,12 +968,57 @@ int tp_autotune(const tp_sample *samples, int32_t nsamples, int32_t precision, v
             overall = bt;
         }
     }
+    // the per-group combination against every single shape on the whole plan
+    // (groups interact through the tails between their launches)
+    auto measure_all = [&](const std::vector<tp_tuning> &gtu, int trials, float &ms) -> int {
+        int r = launch_plan(d, *p, gtu, precision, 0, ws, st);
+        ms = 1e30f;
+        for (int trial = 0; trial < trials && !r; ++trial) {
+            TP_HIP(hipEventRecord(a, st));
+            for (int k = 0; k < 3 && !r; ++k) r = launch_plan(d, *p, gtu, precision, 0, ws, st);
+            TP_HIP(hipEventRecord(b, st));
+            TP_HIP(hipEventSynchronize(b));
+            float m = 0;
+            TP_HIP(hipEventElapsedTime(&m, a, b));
+            ms = std::min(ms, m / 3);
+        }
+        return r;
+    };
+    if (!rc && p && p->groups.size() > 1) {
+        std::vector<tp_tuning> per(p->groups.size());
+        for (size_t g = 0; g < per.size(); ++g) per[g] = d.tuned[group_key(*p, p->groups[g], precision)];
+        float per_ms = 0;
+        rc = measure_all(per, 3, per_ms);
+        float uni_ms = 1e30f;
+        tp_tuning uni = cand[0];
+        for (size_t c = 0; c < cand.size() && !rc; ++c) {
+            float ms = 0;
+            rc = measure_all(std::vector<tp_tuning>(p->groups.size(), cand[c]), 2, ms);
+            if (ms < uni_ms) {
+                uni_ms = ms;
+                uni = cand[c];
+            }
+        }
+        if (!rc) {
+            float again = 0;
+            rc = measure_all(std::vector<tp_tuning>(p->groups.size(), uni), 3, again);
+            uni_ms = std::min(uni_ms, again);
+        }
+        if (!rc && uni_ms < per_ms) {
+            for (size_t g = 0; g < per.size(); ++g) d.tuned[group_key(*p, p->groups[g], precision)] = uni;
+            overall = uni;
+        }
+        static const bool verbose = std::getenv("TP_TUNE_VERBOSE") != nullptr;
+        if (verbose)
+            std::fprintf(stderr, "tp_tune: whole plan per-group %.4f ms, best single shape %.4f ms (epl %d wg/cu %d "
+                         "copies %d)\n", per_ms, uni_ms, uni.unroll, uni.wg_per_cu, uni.lds_copies);
+    }
     g_timing.on = was_on;
     hipEventDestroy(a);
     hipEventDestroy(b);
     if (rc) return rc;
     // the whole request's entry (for callers that pass it explicitly): the
-    // largest group's shape
+    // largest group's shape, or the single shape that won
     *best = overall;
     d.tuned[tune_key(rq, precision)] = overall;
     save_tune_file(d);

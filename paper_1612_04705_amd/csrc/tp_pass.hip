@@ -81,8 +81,11 @@ __device__ __forceinline__ void minors_f64(const double (&a)[4], const double (&
 // signs + - + + - +.  With exact products each minor is correctly rounded and
 // |s - det| <= 8.1 u S; with Kahan minors (float64 inputs) 10.1 u S plus
 // underflow terms, S = sum |m01_k| |m23_(5-k)|.
+// Sm > 0: a bound S <= Sm supplied by the caller (the product of the two
+// minors' L1 norms bounds S); otherwise S is formed here.
 template <bool EXACT_PRODUCTS>
-__device__ __forceinline__ bool det_f64(const double (&m01)[6], const double (&m23)[6], double &det)
+__device__ __forceinline__ bool det_f64(const double (&m01)[6], const double (&m23)[6], double &det,
+                                        double Sm = 0.0)
 {
     double s = m01[0] * m23[5];
     s = fma(-m01[1], m23[4], s);
@@ -90,9 +93,12 @@ __device__ __forceinline__ bool det_f64(const double (&m01)[6], const double (&m
     s = fma(m01[3], m23[2], s);
     s = fma(-m01[4], m23[1], s);
     s = fma(m01[5], m23[0], s);
-    double S = dabs(m01[0]) * dabs(m23[5]);
+    double S = Sm;
+    if (!(Sm > 0.0)) {
+        S = dabs(m01[0]) * dabs(m23[5]);
 #pragma unroll
-    for (int k = 1; k < 6; ++k) S = fma(dabs(m01[k]), dabs(m23[5 - k]), S);
+        for (int k = 1; k < 6; ++k) S = fma(dabs(m01[k]), dabs(m23[5 - k]), S);
+    }
     const double bound = EXACT_PRODUCTS ? (10.0 * U64) * S : fma(12.0 * U64, S, 0x1p-160);
     det = s;
     return dabs(s) > bound;
@@ -207,14 +213,18 @@ __device__ __forceinline__ void covector(const double (&P)[4], const double (&m)
     C[3] = fma(-P[2], m[0], fma(P[1], m[1], -(P[0] * m[3])));
 }
 
-__device__ __forceinline__ int bin_absphi_bv(const double (&m01)[6], const double (&m23)[6], const double (&P)[4],
-                                             double W, const double *edges, int n, bool &sure)
+__device__ __forceinline__ double l1norm6(const double (&m)[6])
+{
+    return ((dabs(m[0]) + dabs(m[1])) + (dabs(m[2]) + dabs(m[3]))) + (dabs(m[4]) + dabs(m[5]));
+}
+
+// M1, M2s: L1 norms of m01, m23
+__device__ __forceinline__ int bin_absphi_bv(const double (&m01)[6], const double (&m23)[6], double M1, double M2s,
+                                             const double (&P)[4], double W, const double *edges, int n, bool &sure)
 {
     double C1[4], C2[4];
     covector(P, m01, C1);
     covector(P, m23, C2);
-    const double M1 = ((dabs(m01[0]) + dabs(m01[1])) + (dabs(m01[2]) + dabs(m01[3]))) + (dabs(m01[4]) + dabs(m01[5]));
-    const double M2s = ((dabs(m23[0]) + dabs(m23[1])) + (dabs(m23[2]) + dabs(m23[3]))) + (dabs(m23[4]) + dabs(m23[5]));
     const double eabs = fma(TINY, W, TINY);
     const double eC1 = fma((7.2 * U64) * W, M1, eabs);
     const double eC2 = fma((7.2 * U64) * W, M2s, eabs);
@@ -248,8 +258,8 @@ __device__ __forceinline__ int bin_absphi_bv(const double (&m01)[6], const doubl
 // SLOT0: the slot is kernel slot 0 (the host relabels the slots so), else s.
 template <bool SLOT0>
 __device__ __forceinline__ int bin_abscos(const double x[4][4], const double w[4], double W,
-                                          const double P[4], double M2, double eM, double kdot,
-                                          int s, const double *edges, int n, bool &sure)
+                                          const double P[4], double M2, int s, const double *edges, int n,
+                                          bool &sure)
 {
     double xs[4];
     double ws = w[0];
@@ -270,22 +280,25 @@ __device__ __forceinline__ int bin_abscos(const double x[4][4], const double w[4
             ws = w[3];
         }
     }
-    const double u2 = 2.01 * U64;
+    // Bounds from magnitudes (W = L1 norm of all components, w_s of slot s;
+    // |P_c| <= W, |P.p_s| <= W w_s, |M^2| <= W^2, |p_s.p_s| <= w_s^2):
+    //   |P.p_s^ - P.p_s| <= (4.01 + 2.01) u W w_s (four roundings, P's error),
+    //   |E_P^ - E_P| <= 2.01 u W, |M^2^ - M^2| <= 10.2 u W^2,
+    //   |d_ss^ - d_ss| <= 4.02 u w_s^2, so with the roundings of the fused steps
+    //   |Nn^ - Nn| <= (2.01 + 6.02 + 10.2 + 3) u W^2 w_s   <= 24 u W^2 w_s,
+    //   |A^ - A|   <= (12.04 + 4.02 + 10.2 + 3) u W^2 w_s^2 <= 32 u W^2 w_s^2,
+    //   |B^ - B|   <= (4.02 + 3.01) u W^2 (+ slack)         <= 10 u W^2.
     const double PPs = mink(P, xs);
-    const double ePP = (7.2 * U64) * W * ws;
-    const double EP = P[0];
-    const double eEP = (3.01 * U64) * W;
     const double Es = xs[0];
     const double dss = mink(xs, xs);
-    const double eds = (kdot * U64) * ws * ws;
-    const double Nn = fma(PPs, EP, -(M2 * Es));
-    const double eNn = fma(dabs(PPs) + ePP, eEP, fma(dabs(EP), ePP,
-                       fma(dabs(Es), eM, fma(u2, dabs(PPs * EP) + dabs(M2 * Es), TINY))));
+    const double Nn = fma(PPs, P[0], -(M2 * Es));
     const double A = fma(PPs, PPs, -(M2 * dss));
-    const double eA = fma(2.0 * dabs(PPs) + ePP, ePP, fma(dabs(M2) + eM, eds,
-                      fma(dabs(dss), eM, fma(u2, PPs * PPs + dabs(M2 * dss), TINY))));
     const double B = fma(P[3], P[3], fma(P[2], P[2], P[1] * P[1]));
-    const double eB = fma(6.1 * U64 * W, W, fma(3.1 * U64, B, TINY));
+    const double WW = W * W;
+    const double Q = WW * ws;
+    const double eNn = fma(24.0 * U64, Q, TINY);
+    const double eA = fma((32.0 * U64) * Q, ws, TINY);
+    const double eB = fma(10.0 * U64, WW, TINY);
     bool ok = (A > eA) && (B > eB);
     const double D = A * B;
     const double eD = fma(A + eA, eB, fma(B, eA, fma(U64, D, TINY)));
@@ -351,14 +364,13 @@ struct Seg {
 // One axis of compile-time kind KIND: bin index, or -1 (out of range).
 template <int KIND, bool EXACTP, bool SLOT0>
 __device__ __forceinline__ int axis_bin(const double (&x)[4][4], const double (&w)[4], double W,
-                                        const double (&m01)[6], const double (&m23)[6],
-                                        const double (&P)[4], double M2, double eM, int nb, int sl,
+                                        const double (&m01)[6], const double (&m23)[6], double M1, double M2s,
+                                        const double (&P)[4], double M2, int nb, int sl,
                                         const double *ed, double glo, double ginv, bool &sure)
 {
-    constexpr double KDOT = EXACTP ? 3.02 : 4.02;
-    if constexpr (KIND == AX_ABSPHI) return bin_absphi_bv(m01, m23, P, W, ed, nb, sure);
+    if constexpr (KIND == AX_ABSPHI) return bin_absphi_bv(m01, m23, M1, M2s, P, W, ed, nb, sure);
     else if constexpr (KIND == AX_MASS) return bin_mass(x, w, sl, ed, nb, glo, ginv, sure);
-    else return bin_abscos<SLOT0>(x, w, W, P, M2, eM, KDOT, sl, ed, nb, sure);
+    else return bin_abscos<SLOT0>(x, w, W, P, M2, sl, ed, nb, sure);
 }
 
 // Whole event, with the binning scheme (K0, K1; AX_NONE = absent) fixed at
@@ -401,6 +413,7 @@ __device__ __forceinline__ EvOut eval_event(const Tin (&q)[4][4], int tag, const
     constexpr bool NEED_BV = K0 == AX_ABSPHI || K1 == AX_ABSPHI;
     constexpr bool F32_SIGN = PREC == 1 && !NEED_BV;
     double m01[6], m23[6];
+    double M1 = 0.0, M2s = 0.0;
     double det;
     bool sure;
     if constexpr (F32_SIGN) {
@@ -421,7 +434,13 @@ __device__ __forceinline__ EvOut eval_event(const Tin (&q)[4][4], int tag, const
     } else {
         minors_f64<EXACTP>(x[0], x[1], m01);
         minors_f64<EXACTP>(x[2], x[3], m23);
-        sure = det_f64<EXACTP>(m01, m23, det);
+        if constexpr (NEED_BV) {
+            M1 = l1norm6(m01);
+            M2s = l1norm6(m23);
+            sure = det_f64<EXACTP>(m01, m23, det, M1 * M2s);
+        } else {
+            sure = det_f64<EXACTP>(m01, m23, det);
+        }
     }
     const double ct = g.sigma > 0 ? det : -det;
     o.ct = ct;
@@ -433,17 +452,16 @@ __device__ __forceinline__ EvOut eval_event(const Tin (&q)[4][4], int tag, const
         o.bin = 0;
         return o;
     } else {
-        const double eM = (10.2 * U64) * W * W;
         bool bsure = true;
         o.why = 3;
         // the first |cos theta| axis reads kernel slot 0 (host relabelling)
-        const int j0 = axis_bin<K0, EXACTP, true>(x, w, W, m01, m23, P, M2, eM, g.nb0, g.slots0, g.e0, g.glo0, g.ginv0,
+        const int j0 = axis_bin<K0, EXACTP, true>(x, w, W, m01, m23, M1, M2s, P, M2, g.nb0, g.slots0, g.e0, g.glo0, g.ginv0,
                                             bsure);
         bool oor = j0 < 0;
         int bin = j0 < 0 ? 0 : j0;
         if constexpr (K1 != AX_NONE) {
             if (bsure) o.why = 4;
-            const int j1 = axis_bin<K1, EXACTP, K0 != AX_ABSCOS>(x, w, W, m01, m23, P, M2, eM, g.nb1, g.slots1, g.e1, g.glo1,
+            const int j1 = axis_bin<K1, EXACTP, K0 != AX_ABSCOS>(x, w, W, m01, m23, M1, M2s, P, M2, g.nb1, g.slots1, g.e1, g.glo1,
                                                 g.ginv1, bsure);
             oor = oor || j1 < 0;
             bin = bin * g.nb1 + (j1 < 0 ? 0 : j1);
