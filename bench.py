@@ -33,7 +33,7 @@ def log(*a):
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ("tp_pass.hip", "tp_kernel.h"):
+    for f in ("tp_pass.hip", "tp_kernel.h", "tp_host.cpp"):
         with open(os.path.join(ROOT, "paper_1612_04705_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -116,7 +116,7 @@ def main():
     ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--cpu-events", type=float, default=6e6)
+    ap.add_argument("--cpu-events", type=float, default=2.5e7)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tuning", default=None,
                     help="fixed launch shape block,wg_per_cu,lds_copies,events_per_lane (skips the autotuner)")
