@@ -1,0 +1,102 @@
+"""CPU oracle of the energy test -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s CPU baseline may
+use this module.  It shares no code with the HIP path.
+
+Follows the paper's Sect. 2.2 (energy test) and Sect. 4 (background) directly:
+
+* coordinates: invariant masses of particle combinations (Sect. 4, Table 1),
+  computed from the stored four-vectors in float64;
+* psi_ij = exp(-d_ij^2 / (2 sigma^2)), d_ij the Euclidean distance between the
+  coordinate vectors of events i and j (Sect. 2.2);
+* T of eq. (2): the two within-sample averages over pairs i < j minus the
+  cross-sample average over all pairs;
+* T of eq. (3): the same with the background-sample terms, written as double
+  sums over ordered pairs (j != i within a sample) with the paper's factors;
+* permutation p-value: the fraction of permutation T values above the observed
+  one (Sect. 2.2).
+
+All sums are plain float64 over explicit pairs (blocked only to bound memory).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def invariant_masses(comps, masks):
+    """Invariant mass of the slots in each bit mask, per event.
+
+    comps: [4 slots][4 comps (E, px, py, pz)][n]; masks: iterable of slot bit
+    masks.  Returns float64 [len(masks)][n]; m = sqrt(max(m^2, 0)).
+    """
+    x = np.asarray(comps, dtype=np.float64)
+    out = []
+    for m in masks:
+        S = np.zeros((4, x.shape[2]))
+        for s in range(4):
+            if m & (1 << s):
+                S += x[s]
+        m2 = S[0] ** 2 - S[1] ** 2 - S[2] ** 2 - S[3] ** 2
+        out.append(np.sqrt(np.maximum(m2, 0.0)))
+    return np.array(out)
+
+
+def psi_block(Ya, Yb, sigma):
+    """psi for every pair of a block: Ya [D][na], Yb [D][nb] -> [na][nb]."""
+    d2 = np.zeros((Ya.shape[1], Yb.shape[1]))
+    for k in range(Ya.shape[0]):
+        diff = Ya[k][:, None] - Yb[k][None, :]
+        d2 += diff * diff
+    return np.exp(-d2 / (2.0 * sigma * sigma))
+
+
+def pair_sum(Ya, Yb, sigma, same, block=2048):
+    """sum of psi over pairs: same sample (Ya is Yb): ordered pairs with j != i;
+    different samples: all pairs (i in a, j in b)."""
+    Ya = np.asarray(Ya, dtype=np.float64)
+    Yb = np.asarray(Yb, dtype=np.float64)
+    na, nb = Ya.shape[1], Yb.shape[1]
+    tot = 0.0
+    for i0 in range(0, na, block):
+        for j0 in range(0, nb, block):
+            p = psi_block(Ya[:, i0:i0 + block], Yb[:, j0:j0 + block], sigma)
+            if same and i0 == j0:
+                np.fill_diagonal(p, 0.0)
+            tot += float(p.sum())
+    return tot
+
+
+def T_eq2(Y, label, sigma):
+    """eq. (2): samples are the events with label 1 (n of them) and label 0
+    (nbar).  Within-sample sums run over pairs i < j."""
+    Y = np.asarray(Y, dtype=np.float64)
+    label = np.asarray(label).astype(bool)
+    X, Xb = Y[:, label], Y[:, ~label]
+    n, nb = X.shape[1], Xb.shape[1]
+    s_xx = 0.5 * pair_sum(X, X, sigma, True)          # pairs i < j
+    s_bb = 0.5 * pair_sum(Xb, Xb, sigma, True)
+    s_xb = pair_sum(X, Xb, sigma, False)
+    return s_xx / (n * (n - 1)) + s_bb / (nb * (nb - 1)) - s_xb / (n * nb)
+
+
+def T_eq3(main, main_bar, bkg, bkg_bar, b, b_bar, sigma):
+    """eq. (3): main samples (n, nbar events) contain b and b_bar background
+    events; background samples hold b_s and b_s_bar events.  w = n - b signal
+    events (w_bar likewise).  Within-sample double sums run over j != i."""
+    n, nb = main.shape[1], main_bar.shape[1]
+    bs, bsb = bkg.shape[1], bkg_bar.shape[1]
+    w, wb = n - b, nb - b_bar
+    S = lambda A, B, same=False: pair_sum(A, B, sigma, same)
+    t1 = (S(main, main, True) - 2.0 * b / bs * S(main, bkg)
+          + b * (b + 1.0) / (bs * (bs - 1.0)) * S(bkg, bkg, True)) / (2.0 * w * (w - 1.0))
+    t2 = (S(main_bar, main_bar, True) - 2.0 * b_bar / bsb * S(main_bar, bkg_bar)
+          + b_bar * (b_bar + 1.0) / (bsb * (bsb - 1.0)) * S(bkg_bar, bkg_bar, True)) / (2.0 * wb * (wb - 1.0))
+    t3 = (S(main, main_bar) - b_bar / bsb * S(main, bkg_bar) - b / bs * S(bkg, main_bar)
+          + b * b_bar / (bs * bsb) * S(bkg, bkg_bar)) / (w * wb)
+    return t1 + t2 - t3
+
+
+def p_value(T_obs, T_perm):
+    """Fraction of permutation T values greater than the observed one."""
+    T_perm = np.asarray(T_perm, dtype=np.float64)
+    return float(np.count_nonzero(T_perm > T_obs)) / len(T_perm)
