@@ -1,0 +1,39 @@
+// Launch layout of the energy-test kernels (internal to libtpasym).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tpe {
+
+enum { MAXD = 8, MAXR = 3 };
+
+// Pair-sum launch: coordinates Y [D][ldY] (float32, device), columns G [n][C]
+// (uint8 0/1, device, C a multiple of 32, at most 128), R row-weight columns
+// (rowcol[r] < 0: weight 1), output sums [C][1 + R] (float64, device, +=).
+struct EParams {
+    const float *Y;
+    int64_t ldY;
+    int64_t n;
+    int32_t D, C, R;
+    int32_t rowcol[MAXR];
+    float kexp;               // -log2(e) / (2 sigma^2)
+    const uint8_t *G;
+    double *sums;
+};
+
+// Coordinate launch: invariant masses of ncoord slot masks per event.
+struct CParams {
+    const void *p[16];        // [slot * 4 + component], device
+    int64_t n;
+    int32_t ncoord;
+    int32_t masks[MAXD];
+    double scale;             // unit factor applied to the masses
+    float *out;               // [ncoord][ldo], device
+    int64_t ldo;
+};
+
+hipError_t launch_pairsums(const EParams &p, hipStream_t st);
+hipError_t launch_coords(const CParams &c, int dtype, hipStream_t st);
+
+}  // namespace tpe

@@ -26,6 +26,8 @@ hipError_t launch_exact(int dtype, int mode, const KParams &kp, int grid, hipStr
 
 using namespace tpk;
 
+#include "tp_energy.h"
+
 namespace {
 
 thread_local std::string g_err;
@@ -1165,5 +1167,130 @@ const char *tp_strerror(int status)
 }
 
 int tp_version(void) { return TPASYM_VERSION; }
+
+// ------------------------------------------------------------ energy test
+int tp_coords(const tp_events *ev, const int32_t *masks, int32_t ncoord, double scale, float *coords, int64_t ld,
+              void *stream)
+{
+    if (!ev || !masks || !coords) return fail(TP_EINVAL, "null pointer");
+    if (ev->n < 0 || ev->n >= (int64_t(1) << 40)) return fail(TP_ERANGE, "n out of range");
+    if (ev->dtype != TP_F32 && ev->dtype != TP_F64) return fail(TP_EINVAL, "dtype must be TP_F32 or TP_F64");
+    if (ncoord < 1 || ncoord > tpe::MAXD) return fail(TP_ERANGE, "ncoord must be 1..8");
+    if (ld < ev->n) return fail(TP_EINVAL, "ld < n");
+    if (!(scale > 0.0) || !std::isfinite(scale)) return fail(TP_EINVAL, "scale must be positive and finite");
+    tpe::CParams c;
+    std::memset(&c, 0, sizeof c);
+    for (int k = 0; k < ncoord; ++k) {
+        if (masks[k] < 1 || masks[k] > 15) return fail(TP_EINVAL, "mask must be a nonzero 4-bit slot mask");
+        c.masks[k] = masks[k];
+    }
+    if (ev->n == 0) return TP_OK;
+    for (int s = 0; s < 4; ++s)
+        for (int q = 0; q < 4; ++q) {
+            if (!ev->p[s][q]) return fail(TP_EINVAL, "component pointer is NULL");
+            c.p[s * 4 + q] = ev->p[s][q];
+        }
+    c.n = ev->n;
+    c.ncoord = ncoord;
+    c.scale = scale;
+    c.out = coords;
+    c.ldo = ld;
+    TP_HIP(tpe::launch_coords(c, ev->dtype, static_cast<hipStream_t>(stream)));
+    return TP_OK;
+}
+
+int tp_pairsums(const float *coords, int32_t dims, int64_t ld, int64_t n, double sigma, const uint8_t *cols,
+                int32_t ncols, const int32_t *rowcols, int32_t nrow, double *sums, void *stream)
+{
+    if (!coords || !cols || !sums || (nrow > 0 && !rowcols)) return fail(TP_EINVAL, "null pointer");
+    if (dims < 1 || dims > tpe::MAXD) return fail(TP_ERANGE, "dims must be 1..8");
+    if (n < 0 || n >= (int64_t(1) << 40)) return fail(TP_ERANGE, "n out of range");
+    if (ld < n) return fail(TP_EINVAL, "ld < n");
+    if (ncols != 32 && ncols != 64 && ncols != 128) return fail(TP_EINVAL, "ncols must be 32, 64 or 128");
+    if (nrow < 0 || nrow > tpe::MAXR) return fail(TP_ERANGE, "nrow must be 0..3");
+    if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(TP_EINVAL, "sigma must be positive and finite");
+    tpe::EParams p;
+    std::memset(&p, 0, sizeof p);
+    for (int r = 0; r < nrow; ++r) {
+        if (rowcols[r] >= ncols) return fail(TP_EINVAL, "row-weight column out of range");
+        p.rowcol[r] = rowcols[r] < 0 ? -1 : rowcols[r];
+    }
+    if (n < 2) return TP_OK;
+    p.Y = coords;
+    p.ldY = ld;
+    p.n = n;
+    p.D = dims;
+    p.C = ncols;
+    p.R = nrow;
+    // psi = exp(-d^2 / (2 sigma^2)) = 2^(d^2 * kexp)
+    p.kexp = (float)(-1.4426950408889634 / (2.0 * sigma * sigma));
+    p.G = cols;
+    p.sums = sums;
+    TP_HIP(tpe::launch_pairsums(p, static_cast<hipStream_t>(stream)));
+    return TP_OK;
+}
+
+int tp_energy_eq2(const double *sums, int32_t ncols, int32_t nrow, int32_t ones_row, int32_t ones_col,
+                  const int64_t *nx, int64_t n, double *T)
+{
+    if (!sums || !nx || !T) return fail(TP_EINVAL, "null pointer");
+    if (ncols < 1 || nrow < 1 || ones_row < 0 || ones_row >= nrow || ones_col < 0 || ones_col >= ncols)
+        return fail(TP_EINVAL, "bad column or row index");
+    const int w = 1 + nrow;
+    const double tot = sums[(int64_t)ones_col * w + 1 + ones_row];     // sum over i != j of psi
+    for (int c = 0; c < ncols; ++c) {
+        const double q = sums[(int64_t)c * w];                         // both in X, ordered
+        const double r = sums[(int64_t)c * w + 1 + ones_row];          // j in X, i anywhere
+        const double a = (double)nx[c], b = (double)(n - nx[c]);
+        if (nx[c] < 2 || n - nx[c] < 2) {
+            T[c] = NAN;
+            continue;
+        }
+        const double sxx = 0.5 * q, sbb = 0.5 * (tot - 2.0 * r + q), sxb = r - q;
+        T[c] = sxx / (a * (a - 1.0)) + sbb / (b * (b - 1.0)) - sxb / (a * b);
+    }
+    return TP_OK;
+}
+
+int tp_energy_eq3(const double *sums, int32_t ncols, int32_t nrow, int32_t col_main, int32_t col_bkg,
+                  int32_t row_main, int32_t row_bkg, const int32_t *perm_cols, int32_t nperm, int64_t n_main,
+                  int64_t n_main_bar, int64_t n_bkg, int64_t n_bkg_bar, double b, double b_bar, double *T)
+{
+    if (!sums || !perm_cols || !T) return fail(TP_EINVAL, "null pointer");
+    if (col_main < 0 || col_main >= ncols || col_bkg < 0 || col_bkg >= ncols || row_main < 0 || row_main >= nrow ||
+        row_bkg < 0 || row_bkg >= nrow || nperm < 0)
+        return fail(TP_EINVAL, "bad column or row index");
+    const int w = 1 + nrow;
+    auto at = [&](int c, int q) { return sums[(int64_t)c * w + q]; };
+    const double Smm = at(col_main, 1 + row_main), Smk = at(col_bkg, 1 + row_main), Skk = at(col_bkg, 1 + row_bkg);
+    const double ws = (double)n_main - b, wsb = (double)n_main_bar - b_bar;
+    const double bs = (double)n_bkg, bsb = (double)n_bkg_bar;
+    for (int k = 0; k < nperm; ++k) {
+        const int ca = perm_cols[3 * k], cb = perm_cols[3 * k + 1], cg = perm_cols[3 * k + 2];
+        if (ca < 0 || ca >= ncols || cb < 0 || cb >= ncols || cg < 0 || cg >= ncols)
+            return fail(TP_EINVAL, "permutation column out of range");
+        // ordered-pair sums (j != i) between the four samples, from the column sums:
+        // a = main X, abar = main - a, beta = bkg X, betabar = bkg - beta, gamma = a + beta
+        const double Saa = at(ca, 0), Sbb = at(cb, 0);
+        const double Sab = 0.5 * (at(cg, 0) - Saa - Sbb);
+        const double Sam = at(ca, 1 + row_main), Sak = at(ca, 1 + row_bkg);
+        const double Sbm = at(cb, 1 + row_main), Sbk = at(cb, 1 + row_bkg);
+        const double main_x = Saa, main_xb = Smm - 2.0 * Sam + Saa;
+        const double bkg_x = Sbb, bkg_xb = Skk - 2.0 * Sbk + Sbb;
+        const double mx_bx = Sab;                                  // main X with bkg X
+        const double mxb_bxb = Smk - Sbm - Sak + Sab;              // main Xbar with bkg Xbar
+        const double mx_mxb = Sam - Saa;                           // main X with main Xbar
+        const double mx_bxb = Sak - Sab;                           // main X with bkg Xbar
+        const double bx_mxb = Sbm - Sab;                           // bkg X with main Xbar
+        const double bx_bxb = Sbk - Sbb;                           // bkg X with bkg Xbar
+        const double t1 = (main_x - 2.0 * b / bs * mx_bx + b * (b + 1.0) / (bs * (bs - 1.0)) * bkg_x) /
+                          (2.0 * ws * (ws - 1.0));
+        const double t2 = (main_xb - 2.0 * b_bar / bsb * mxb_bxb + b_bar * (b_bar + 1.0) / (bsb * (bsb - 1.0)) * bkg_xb) /
+                          (2.0 * wsb * (wsb - 1.0));
+        const double t3 = (mx_mxb - b_bar / bsb * mx_bxb - b / bs * bx_mxb + b * b_bar / (bs * bsb) * bx_bxb) / (ws * wsb);
+        T[k] = t1 + t2 - t3;
+    }
+    return TP_OK;
+}
 
 }  // extern "C"

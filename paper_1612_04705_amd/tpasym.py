@@ -97,6 +97,17 @@ def load():
         "tp_release": [],
         "tp_strerror": [ctypes.c_int],
         "tp_version": [],
+        "tp_coords": [P(_Events), P(ctypes.c_int32), ctypes.c_int32, ctypes.c_double, ctypes.c_void_p,
+                      ctypes.c_int64, ctypes.c_void_p],
+        "tp_pairsums": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
+                        ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_int32), ctypes.c_int32, ctypes.c_void_p,
+                        ctypes.c_void_p],
+        "tp_energy_eq2": [P(ctypes.c_double), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                          P(ctypes.c_int64), ctypes.c_int64, P(ctypes.c_double)],
+        "tp_energy_eq3": [P(ctypes.c_double), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                          ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int32), ctypes.c_int32, ctypes.c_int64,
+                          ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                          P(ctypes.c_double)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -108,7 +119,8 @@ def load():
 
 def exported_symbols():
     return ("tp_compute", "tp_bin", "tp_asym", "tp_scp", "tp_batch", "tp_autotune", "tp_timing_enable",
-            "tp_timing_reset", "tp_timing_read", "tp_release", "tp_strerror", "tp_version")
+            "tp_timing_reset", "tp_timing_read", "tp_release", "tp_strerror", "tp_version", "tp_coords",
+            "tp_pairsums", "tp_energy_eq2", "tp_energy_eq3")
 
 
 def _check(rc):
@@ -290,3 +302,58 @@ def release():
 
 def version():
     return int(load().tp_version())
+
+
+# ------------------------------------------------------------------ energy test
+def coords(ds: DeviceSample, masks, scale=1e-3, out=None, stream=None):
+    """Invariant masses (x scale) of the slot masks, float32 [len(masks)][n] on the device."""
+    m = (ctypes.c_int32 * len(masks))(*masks)
+    if out is None:
+        out = torch.empty((len(masks), ds.n), dtype=torch.float32, device=ds.tag.device)
+    e = ds.events()
+    _check(load().tp_coords(ctypes.byref(e), m, len(masks), float(scale), ctypes.c_void_p(out.data_ptr()),
+                            out.stride(0), _stream(stream)))
+    return out
+
+
+def pairsums(Y, cols, sigma, rowcols=(-1,), sums=None, stream=None):
+    """Pair sums over the columns of ``cols`` (uint8 [n][C] on the device) for coordinates
+    Y (float32 [D][ld] on the device); returns float64 [C][1 + len(rowcols)] (accumulated)."""
+    if Y.dtype != torch.float32 or cols.dtype != torch.uint8 or not cols.is_contiguous() or Y.stride(1) != 1:
+        raise TPError("Y must be float32 with unit inner stride, cols contiguous uint8")
+    n, C = cols.shape
+    if sums is None:
+        sums = torch.zeros((C, 1 + len(rowcols)), dtype=torch.float64, device=cols.device)
+    rc = (ctypes.c_int32 * max(1, len(rowcols)))(*rowcols)
+    _check(load().tp_pairsums(ctypes.c_void_p(Y.data_ptr()), Y.shape[0], Y.stride(0), n, float(sigma),
+                              ctypes.c_void_p(cols.data_ptr()), C, rc, len(rowcols),
+                              ctypes.c_void_p(sums.data_ptr()), _stream(stream)))
+    return sums
+
+
+def energy_eq2(sums, nx, n, ones_row=0, ones_col=0):
+    """T of eq. (2) per column from (host) pair sums."""
+    S = np.ascontiguousarray(np.asarray(sums.cpu() if hasattr(sums, "cpu") else sums, dtype=np.float64))
+    C, w = S.shape
+    nxa = np.ascontiguousarray(np.asarray(nx, dtype=np.int64))
+    T = np.empty(C)
+    P = ctypes.POINTER
+    _check(load().tp_energy_eq2(S.ctypes.data_as(P(ctypes.c_double)), C, w - 1, ones_row, ones_col,
+                                nxa.ctypes.data_as(P(ctypes.c_int64)), int(n), T.ctypes.data_as(P(ctypes.c_double))))
+    return T
+
+
+def energy_eq3(sums, col_main, col_bkg, row_main, row_bkg, perm_cols, n_main, n_main_bar, n_bkg, n_bkg_bar,
+               b, b_bar):
+    """T of eq. (3) per permutation (a, beta, gamma) column triple from (host) pair sums."""
+    S = np.ascontiguousarray(np.asarray(sums.cpu() if hasattr(sums, "cpu") else sums, dtype=np.float64))
+    C, w = S.shape
+    pc = np.ascontiguousarray(np.asarray(perm_cols, dtype=np.int32).reshape(-1))
+    k = len(pc) // 3
+    T = np.empty(k)
+    P = ctypes.POINTER
+    _check(load().tp_energy_eq3(S.ctypes.data_as(P(ctypes.c_double)), C, w - 1, col_main, col_bkg, row_main,
+                                row_bkg, pc.ctypes.data_as(P(ctypes.c_int32)), k, int(n_main), int(n_main_bar),
+                                int(n_bkg), int(n_bkg_bar), float(b), float(b_bar),
+                                T.ctypes.data_as(P(ctypes.c_double))))
+    return T

@@ -27,7 +27,7 @@ def tp():
 def header_functions():
     src = open(os.path.join(ROOT, "include", "tpasym.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(tp_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(tp_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_every_declared_symbol_is_exported(tp):

@@ -1,0 +1,153 @@
+"""GPU parity of the energy test (pair sums on the matrix cores) against the oracle.
+
+Tolerance.  The device forms coordinates in float32 (relative rounding 2^-24 of
+masses ~1-2 GeV), psi in float32 with the hardware exp2 (a few ulp), and sums
+each chunk of 2 x 256 products in float32 before float64 accumulation.  Each
+psi is therefore within ~1e-6 relative of the float64 value (the distance
+error d * |delta d| / sigma^2 with |delta d| <~ 4e-7 GeV dominates at
+sigma = 0.3 GeV), and so is each of the three terms of T.  The test allows
+1e-5 of the sum of the three terms' magnitudes.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import energy
+from paper_1612_04705_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+# D0 -> K+ K- pi+ pi- coordinates (Sect. 4): m12, m14, m23, m34, m134
+MASKS = [0b0011, 0b1001, 0b0110, 0b1100, 0b1101]
+
+
+@pytest.fixture(scope="module")
+def tp():
+    from paper_1612_04705_amd import tpasym
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    tpasym.load()
+    return tpasym
+
+
+def sample(n, seed):
+    ch = synth.CHANNELS["D0_KKpipi"]
+    return ch, synth.generate(ch, n, seed, inj=synth.INJ_SGN)
+
+
+def terms(Y, lab, sigma):
+    Y = np.asarray(Y, dtype=np.float64)
+    lab = np.asarray(lab).astype(bool)
+    X, B = Y[:, lab], Y[:, ~lab]
+    n, nb = X.shape[1], B.shape[1]
+    return (0.5 * energy.pair_sum(X, X, sigma, True) / (n * (n - 1)),
+            0.5 * energy.pair_sum(B, B, sigma, True) / (nb * (nb - 1)),
+            energy.pair_sum(X, B, sigma, False) / (n * nb))
+
+
+def test_coords_match_oracle(tp):
+    ch, s = sample(3001, 80)
+    ds = tp.DeviceSample.from_sample(s)
+    Yg = tp.coords(ds, MASKS, 1e-3).cpu().numpy().astype(np.float64)
+    comps, _ = s.numpy()
+    Yo = energy.invariant_masses(comps, MASKS) * 1e-3
+    # float32 output: within 2^-24 of the float64 value beyond the inputs' own rounding
+    W = np.stack([np.abs(comps[[t for t in range(4) if m & (1 << t)]].astype(np.float64)).sum(axis=(0, 1))
+                  for m in MASKS]) * 1e-3
+    tol = 2.0 * W * W * 2.0 ** -53 * 64 / np.maximum(Yo, 1e-3) + 2.0 ** -23 * Yo
+    assert np.all(np.abs(Yg - Yo) <= tol)
+
+
+@pytest.mark.parametrize("n,sigma", [(2000, 0.3), (1277, 0.8)])
+def test_eq2_observed_and_permutations(tp, n, sigma):
+    ch, s = sample(n, 81 + n)
+    ds = tp.DeviceSample.from_sample(s)
+    # P-odd split (Sect. 5): X = classes I and IV, Xbar = II and III
+    cls, _, _ = tp.compute(ds, tp.channel(ch.triple, ch.planes), tp.TP_PREC_F64)
+    cls = cls.cpu().numpy()
+    assert np.all(cls < 4)
+    lab = ((cls == 0) | (cls == 3)).astype(np.uint8)
+    rng = np.random.default_rng(7)
+    nperm = 14
+    C = 32
+    cols = np.zeros((n, C), dtype=np.uint8)
+    cols[:, 0] = 1                      # all ones
+    cols[:, 1] = lab
+    perms = [rng.permutation(lab) for _ in range(nperm)]
+    for k, pl in enumerate(perms):
+        cols[:, 2 + k] = pl
+    Yg = tp.coords(ds, MASKS, 1e-3)
+    sums = tp.pairsums(Yg, torch.from_numpy(cols).cuda(), sigma, rowcols=(-1,))
+    torch.cuda.synchronize()
+    T = tp.energy_eq2(sums, cols.sum(axis=0), n, ones_row=0, ones_col=0)
+    comps, _ = s.numpy()
+    Yo = energy.invariant_masses(comps, MASKS) * 1e-3
+    want = [energy.T_eq2(Yo, lab, sigma)] + [energy.T_eq2(Yo, pl, sigma) for pl in perms]
+    for k, w in enumerate(want):
+        a, b, c = terms(Yo, lab if k == 0 else perms[k - 1], sigma)
+        tol = 1e-5 * (abs(a) + abs(b) + abs(c))
+        assert abs(T[1 + k] - w) <= tol, (k, T[1 + k], w, tol)
+    # p-value: permutations strictly above the observed T; a permutation whose
+    # oracle T lies within the tolerance of the observed one may go either way
+    tol0 = 1e-5 * sum(abs(t) for t in terms(Yo, lab, sigma))
+    sure = [abs(w - want[0]) > 2 * tol0 for w in want[1:]]
+    got_above = [T[2 + k] > T[1] for k in range(nperm)]
+    want_above = [w > want[0] for w in want[1:]]
+    assert all(g == w for g, w, s_ in zip(got_above, want_above, sure) if s_)
+
+
+def test_eq2_sigma_infinite_is_zero(tp):
+    ch, s = sample(777, 90)
+    ds = tp.DeviceSample.from_sample(s)
+    lab = (np.arange(777) % 3 == 0).astype(np.uint8)
+    cols = np.zeros((777, 32), dtype=np.uint8)
+    cols[:, 0] = 1
+    cols[:, 1] = lab
+    sums = tp.pairsums(tp.coords(ds, MASKS, 1e-3), torch.from_numpy(cols).cuda(), 1e12)
+    torch.cuda.synchronize()
+    S = sums.cpu().numpy()
+    # every psi is exactly 1: ordered-pair counts
+    assert S[0, 1] == 777 * 776 and S[1, 0] == lab.sum() * (lab.sum() - 1)
+    T = tp.energy_eq2(S, cols.sum(axis=0), 777)
+    assert abs(T[1]) < 1e-15
+
+
+def test_eq3_against_oracle(tp):
+    # main samples with background, background samples from a flat (different) source
+    ch, sig = sample(1500, 91)
+    _, bk = sample(900, 92)
+    ds_s, ds_b = tp.DeviceSample.from_sample(sig), tp.DeviceSample.from_sample(bk)
+    Ys = tp.coords(ds_s, MASKS, 1e-3)
+    Yb = tp.coords(ds_b, MASKS, 1e-3)
+    rng = np.random.default_rng(11)
+    fl_main = (rng.uniform(size=1500) < 0.6).astype(np.uint8)     # flavour X in the main samples
+    fl_bkg = (rng.uniform(size=900) < 0.6).astype(np.uint8)
+    n = 2400
+    Y = torch.cat([Ys, Yb], dim=1).contiguous()
+    main = np.r_[np.ones(1500), np.zeros(900)].astype(np.uint8)
+    bkgc = 1 - main
+    perms = [(fl_main, fl_bkg)] + [(rng.permutation(fl_main), rng.permutation(fl_bkg)) for _ in range(5)]
+    C = 32
+    cols = np.zeros((n, C), dtype=np.uint8)
+    cols[:, 0], cols[:, 1] = main, bkgc
+    triples = []
+    for k, (fm, fb) in enumerate(perms):
+        a = np.r_[fm, np.zeros(900)].astype(np.uint8)
+        beta = np.r_[np.zeros(1500), fb].astype(np.uint8)
+        cols[:, 2 + 3 * k], cols[:, 3 + 3 * k], cols[:, 4 + 3 * k] = a, beta, a + beta
+        triples.append((2 + 3 * k, 3 + 3 * k, 4 + 3 * k))
+    sums = tp.pairsums(Y, torch.from_numpy(cols).cuda(), 0.4, rowcols=(0, 1))
+    torch.cuda.synchronize()
+    nm, nmb = int(fl_main.sum()), 1500 - int(fl_main.sum())
+    nb_, nbb = int(fl_bkg.sum()), 900 - int(fl_bkg.sum())
+    b, b_bar = 0.3 * nm, 0.3 * nmb
+    T = tp.energy_eq3(sums, 0, 1, 0, 1, triples, nm, nmb, nb_, nbb, b, b_bar)
+    cs, _ = sig.numpy()
+    cb, _ = bk.numpy()
+    Yso = energy.invariant_masses(cs, MASKS) * 1e-3
+    Ybo = energy.invariant_masses(cb, MASKS) * 1e-3
+    for k, (fm, fb) in enumerate(perms[:3]):
+        fm, fb = fm.astype(bool), fb.astype(bool)
+        w = energy.T_eq3(Yso[:, fm], Yso[:, ~fm], Ybo[:, fb], Ybo[:, ~fb], b, b_bar, 0.4)
+        # same term-magnitude tolerance as eq. (2), from the no-background terms
+        mag = sum(abs(t) for t in terms(Yso, fm.astype(np.uint8), 0.4))
+        assert abs(T[k] - w) <= 1e-4 * mag, (k, T[k], w)
