@@ -258,10 +258,10 @@ int tp_version(void);
  * d_ij the Euclidean distance between events in phase-space coordinates
  * (invariant masses, Sect. 4 Table 1).  The device computes, for a 0/1 column
  * matrix G [n][ncols] (one column per sample indicator: the observed split,
- * each permutation of it, ...), the pair sums
+ * each permutation of it, ...) whose leading ``nrow`` columns double as row
+ * weights, the pair sums
  *     sums[c][0]     = sum_i sum_{j != i} G[i][c] psi_ij G[j][c]
- *     sums[c][1 + r] = sum_i sum_{j != i} w_r(i)  psi_ij G[j][c],
- *     w_r(i) = G[i][rowcols[r]]  (rowcols[r] < 0: w_r = 1),
+ *     sums[c][1 + q] = sum_i sum_{j != i} G[i][q] psi_ij G[j][c],   q < nrow,
  * from which the host functions form T of eq. (2) per column and T of eq. (3)
  * per permutation.  Permutations are the caller's: random numbers are inputs.
  * ------------------------------------------------------------------------ */
@@ -273,17 +273,19 @@ int tp_coords(const tp_events *ev, const int32_t *masks, int32_t ncoord, double 
               void *stream);
 
 /* Pair sums above.  coords [dims][ld] float32 (device, dims 1..8, ld >= n);
- * cols [n][ncols] uint8 0/1 (device, row-major, ncols 32, 64 or 128);
- * rowcols (host, nrow 0..3 entries); sums [ncols][1 + nrow] float64 (device,
- * accumulated: zero it once).  sigma > 0.  psi is formed in float32 (hardware
- * exp2), products and per-chunk sums on the matrix cores in float32, and
+ * cols [n][ncols] uint8 0/1 (device, row-major, 16-byte aligned, ncols 32, 64
+ * or 128; its first nrow (0..3) columns are also the row weights); sums
+ * [ncols][1 + nrow] float64 (device, accumulated: zero it once).  sigma > 0.
+ * psi is formed in float32 (hardware exp2) for pairs j > i only (psi is
+ * symmetric), products and per-chunk sums on the matrix cores in float32,
  * accumulated across chunks in float64.  Async on ``stream``. */
 int tp_pairsums(const float *coords, int32_t dims, int64_t ld, int64_t n, double sigma, const uint8_t *cols,
-                int32_t ncols, const int32_t *rowcols, int32_t nrow, double *sums, void *stream);
+                int32_t ncols, int32_t nrow, double *sums, void *stream);
 
 /* eq. (2) per column c from host copies of the sums: sample X = events with
  * G[i][c] = 1 (nx[c] of them), Xbar = the other n - nx[c];
- * needs an all-ones column ``ones_col`` and the all-ones row weight ``ones_row``.
+ * needs an all-ones column ``ones_col`` (< nrow, so that it is also row weight
+ * ``ones_row`` = ones_col).
  * T[c] = NaN when a sample has fewer than two events. */
 int tp_energy_eq2(const double *sums, int32_t ncols, int32_t nrow, int32_t ones_row, int32_t ones_col,
                   const int64_t *nx, int64_t n, double *T);
@@ -292,7 +294,7 @@ int tp_energy_eq2(const double *sums, int32_t ncols, int32_t nrow, int32_t ones_
  * col_bkg mark the main and background samples (both flavours); per
  * permutation perm_cols[3k..3k+2] = (a, beta, gamma): a = main events of flavour
  * X, beta = background-sample events of flavour X, gamma = a + beta.  Row
- * weights row_main / row_bkg index rowcols entries equal to col_main / col_bkg.
+ * weights row_main / row_bkg (< nrow) are the same columns as col_main / col_bkg.
  * n_main, n_main_bar: main-sample sizes per flavour; n_bkg, n_bkg_bar:
  * background-sample sizes (b_s, b_s bar); b, b_bar: background events in the
  * main samples.  T[k] for k < nperm. */

@@ -31,9 +31,15 @@ def _hipcc():
     return os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
+# Per-source flags.  The energy kernels keep their MFMA accumulators in the
+# VGPR form: with accumulation registers the compiler copies every tile out of
+# them once per loop iteration.
+SOURCE_FLAGS = {"tp_energy.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
+
 def _compile(name, path, extra, verbose):
     obj = os.path.join(OBJ, os.path.basename(path) + ".o")
-    cmd = [_hipcc(), *FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
+    cmd = [_hipcc(), *FLAGS, *SOURCE_FLAGS.get(name, []), *extra, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
            path, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)

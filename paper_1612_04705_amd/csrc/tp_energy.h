@@ -9,15 +9,14 @@ namespace tpe {
 enum { MAXD = 8, MAXR = 3 };
 
 // Pair-sum launch: coordinates Y [D][ldY] (float32, device), columns G [n][C]
-// (uint8 0/1, device, C a multiple of 32, at most 128), R row-weight columns
-// (rowcol[r] < 0: weight 1), output sums [C][1 + R] (float64, device, +=).
+// (uint8 0/1, device, 16-byte aligned, C 32, 64 or 128), the leading R columns
+// also row weights, output sums [C][1 + R] (float64, device, +=).
 struct EParams {
     const float *Y;
     int64_t ldY;
     int64_t n;
     int32_t D, C, R;
-    int32_t rowcol[MAXR];
-    float kexp;               // -log2(e) / (2 sigma^2)
+    float yscale;             // sqrt(log2(e) / (2 sigma^2)): psi = 2^-(yscale d)^2
     const uint8_t *G;
     double *sums;
 };

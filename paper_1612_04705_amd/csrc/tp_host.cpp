@@ -1200,21 +1200,18 @@ int tp_coords(const tp_events *ev, const int32_t *masks, int32_t ncoord, double 
 }
 
 int tp_pairsums(const float *coords, int32_t dims, int64_t ld, int64_t n, double sigma, const uint8_t *cols,
-                int32_t ncols, const int32_t *rowcols, int32_t nrow, double *sums, void *stream)
+                int32_t ncols, int32_t nrow, double *sums, void *stream)
 {
-    if (!coords || !cols || !sums || (nrow > 0 && !rowcols)) return fail(TP_EINVAL, "null pointer");
+    if (!coords || !cols || !sums) return fail(TP_EINVAL, "null pointer");
     if (dims < 1 || dims > tpe::MAXD) return fail(TP_ERANGE, "dims must be 1..8");
     if (n < 0 || n >= (int64_t(1) << 40)) return fail(TP_ERANGE, "n out of range");
     if (ld < n) return fail(TP_EINVAL, "ld < n");
     if (ncols != 32 && ncols != 64 && ncols != 128) return fail(TP_EINVAL, "ncols must be 32, 64 or 128");
     if (nrow < 0 || nrow > tpe::MAXR) return fail(TP_ERANGE, "nrow must be 0..3");
+    if ((reinterpret_cast<uintptr_t>(cols) & 15u) != 0) return fail(TP_EINVAL, "cols must be 16-byte aligned");
     if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(TP_EINVAL, "sigma must be positive and finite");
     tpe::EParams p;
     std::memset(&p, 0, sizeof p);
-    for (int r = 0; r < nrow; ++r) {
-        if (rowcols[r] >= ncols) return fail(TP_EINVAL, "row-weight column out of range");
-        p.rowcol[r] = rowcols[r] < 0 ? -1 : rowcols[r];
-    }
     if (n < 2) return TP_OK;
     p.Y = coords;
     p.ldY = ld;
@@ -1222,8 +1219,8 @@ int tp_pairsums(const float *coords, int32_t dims, int64_t ld, int64_t n, double
     p.D = dims;
     p.C = ncols;
     p.R = nrow;
-    // psi = exp(-d^2 / (2 sigma^2)) = 2^(d^2 * kexp)
-    p.kexp = (float)(-1.4426950408889634 / (2.0 * sigma * sigma));
+    // psi = exp(-d^2 / (2 sigma^2)) = 2^-(yscale d)^2
+    p.yscale = (float)std::sqrt(1.4426950408889634 / (2.0 * sigma * sigma));
     p.G = cols;
     p.sums = sums;
     TP_HIP(tpe::launch_pairsums(p, static_cast<hipStream_t>(stream)));

@@ -100,8 +100,7 @@ def load():
         "tp_coords": [P(_Events), P(ctypes.c_int32), ctypes.c_int32, ctypes.c_double, ctypes.c_void_p,
                       ctypes.c_int64, ctypes.c_void_p],
         "tp_pairsums": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
-                        ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_int32), ctypes.c_int32, ctypes.c_void_p,
-                        ctypes.c_void_p],
+                        ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p],
         "tp_energy_eq2": [P(ctypes.c_double), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                           P(ctypes.c_int64), ctypes.c_int64, P(ctypes.c_double)],
         "tp_energy_eq3": [P(ctypes.c_double), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -316,17 +315,17 @@ def coords(ds: DeviceSample, masks, scale=1e-3, out=None, stream=None):
     return out
 
 
-def pairsums(Y, cols, sigma, rowcols=(-1,), sums=None, stream=None):
-    """Pair sums over the columns of ``cols`` (uint8 [n][C] on the device) for coordinates
-    Y (float32 [D][ld] on the device); returns float64 [C][1 + len(rowcols)] (accumulated)."""
+def pairsums(Y, cols, sigma, nrow=1, sums=None, stream=None):
+    """Pair sums over the columns of ``cols`` (uint8 [n][C] on the device; its first
+    ``nrow`` columns are also the row weights) for coordinates Y (float32 [D][ld] on
+    the device); returns float64 [C][1 + nrow] (accumulated)."""
     if Y.dtype != torch.float32 or cols.dtype != torch.uint8 or not cols.is_contiguous() or Y.stride(1) != 1:
         raise TPError("Y must be float32 with unit inner stride, cols contiguous uint8")
     n, C = cols.shape
     if sums is None:
-        sums = torch.zeros((C, 1 + len(rowcols)), dtype=torch.float64, device=cols.device)
-    rc = (ctypes.c_int32 * max(1, len(rowcols)))(*rowcols)
+        sums = torch.zeros((C, 1 + nrow), dtype=torch.float64, device=cols.device)
     _check(load().tp_pairsums(ctypes.c_void_p(Y.data_ptr()), Y.shape[0], Y.stride(0), n, float(sigma),
-                              ctypes.c_void_p(cols.data_ptr()), C, rc, len(rowcols),
+                              ctypes.c_void_p(cols.data_ptr()), C, int(nrow),
                               ctypes.c_void_p(sums.data_ptr()), _stream(stream)))
     return sums
 

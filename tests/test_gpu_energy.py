@@ -76,7 +76,7 @@ def test_eq2_observed_and_permutations(tp, n, sigma):
     for k, pl in enumerate(perms):
         cols[:, 2 + k] = pl
     Yg = tp.coords(ds, MASKS, 1e-3)
-    sums = tp.pairsums(Yg, torch.from_numpy(cols).cuda(), sigma, rowcols=(-1,))
+    sums = tp.pairsums(Yg, torch.from_numpy(cols).cuda(), sigma, nrow=1)
     torch.cuda.synchronize()
     T = tp.energy_eq2(sums, cols.sum(axis=0), n, ones_row=0, ones_col=0)
     comps, _ = s.numpy()
@@ -135,7 +135,7 @@ def test_eq3_against_oracle(tp):
         beta = np.r_[np.zeros(1500), fb].astype(np.uint8)
         cols[:, 2 + 3 * k], cols[:, 3 + 3 * k], cols[:, 4 + 3 * k] = a, beta, a + beta
         triples.append((2 + 3 * k, 3 + 3 * k, 4 + 3 * k))
-    sums = tp.pairsums(Y, torch.from_numpy(cols).cuda(), 0.4, rowcols=(0, 1))
+    sums = tp.pairsums(Y, torch.from_numpy(cols).cuda(), 0.4, nrow=2)
     torch.cuda.synchronize()
     nm, nmb = int(fl_main.sum()), 1500 - int(fl_main.sum())
     nb_, nbb = int(fl_bkg.sum()), 900 - int(fl_bkg.sum())
@@ -151,3 +151,28 @@ def test_eq3_against_oracle(tp):
         # same term-magnitude tolerance as eq. (2), from the no-background terms
         mag = sum(abs(t) for t in terms(Yso, fm.astype(np.uint8), 0.4))
         assert abs(T[k] - w) <= 1e-4 * mag, (k, T[k], w)
+
+
+def test_full_size_sampled_sums(tp):
+    """At 1e6 events: a column holding 64 scattered events makes each of its sums
+    O(n x 64) pairs, which the oracle evaluates directly."""
+    n = 1_000_000
+    spec = synth.SampleSpec(synth.CHANNELS["D0_KKpipi"], n, 77, [], inj=synth.INJ_SGN)
+    s = synth.make_sample(spec)
+    ds = tp.DeviceSample.from_sample(s)
+    Y = tp.coords(ds, MASKS, 1e-3)
+    rng = np.random.default_rng(5)
+    pick = np.sort(rng.choice(n, 64, replace=False))
+    cols = np.zeros((n, 32), dtype=np.uint8)
+    cols[:, 0] = 1
+    cols[pick, 1] = 1
+    sums = tp.pairsums(Y, torch.from_numpy(cols).cuda(), 0.3, nrow=1)
+    torch.cuda.synchronize()
+    S = sums.cpu().numpy()
+    comps, _ = s.numpy()
+    Yo = energy.invariant_masses(comps, MASKS) * 1e-3
+    # every event against the picked ones, minus the 64 self-pairs (psi = 1)
+    want_all = energy.pair_sum(Yo, Yo[:, pick], 0.3, False) - 64.0
+    want_diag = energy.pair_sum(Yo[:, pick], Yo[:, pick], 0.3, True)
+    assert abs(S[1, 1] - want_all) <= 1e-5 * want_all
+    assert abs(S[1, 0] - want_diag) <= 1e-5 * want_all
