@@ -105,7 +105,10 @@ def cpu_baseline(samples, budget_events, want_counts_of):
             "seconds": secs}, out
 
 
-MFMA_F32_PEAK_TFLOPS = 157.3   # MI355X dense float32 matrix-core peak
+# MI355X: 256 compute units x 4 SIMDs x 16 lanes x 2.4 GHz, one float32 vector
+# operation per lane per cycle (packed float32 is not used)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+MFMA_F16_PEAK_TFLOPS = 2500.0   # dense float16 matrix-core peak
 
 
 def energy_leg(n, nperm, dev):
@@ -151,18 +154,25 @@ def energy_leg(n, nperm, dev):
     nx = cols.sum(dim=0, dtype=torch.int64).cpu().numpy()
     T = tpasym.energy_eq2(S, nx, n)
     T_obs, T_perm = float(T[1]), T[2:2 + nperm]
-    # psi is symmetric: the kernel forms each unordered pair once and contracts
-    # it with the C columns (one multiply-add per column)
+    # psi is symmetric: the kernel forms each unordered pair once.  Its bound is
+    # the vector ALU evaluating psi: per pair D differences, D multiply-adds and
+    # one exp2 (2 D + 1 lane operations); the contraction with the C columns runs
+    # on the matrix cores as two float16 terms (4 C flops per pair).
     pairs = n * (n - 1) / 2.0
-    flops = 2.0 * pairs * C
+    D = len(masks)
+    ops = (2 * D + 1) * pairs
+    mfma_flops = 4.0 * C * pairs
     log(f"energy test: {n} events, {C} columns, {sec * 1e3:.1f} ms per pass, "
         f"{sec * 1e3 / (nperm + 1):.2f} ms per permutation, T = {T_obs:.4e}")
     return {"events": n, "coordinates": 5, "sigma_GeV": sigma, "columns": C, "permutations": nperm,
             "seconds_per_pass": sec, "ms_per_permutation": sec * 1e3 / (nperm + 1),
             "unordered_pairs_per_s": pairs / sec,
-            "roofline": {"bound": "mfma", "achieved": flops / sec / 1e12, "peak": MFMA_F32_PEAK_TFLOPS,
-                         "unit": "TFLOP/s", "frac": flops / sec / 1e12 / MFMA_F32_PEAK_TFLOPS,
-                         "flops_per_pass": flops, "dtype": "f32 (psi, products), f64 (chunk sums)"},
+            "roofline": {"bound": "alu", "achieved": ops / sec / 1e12, "peak": VALU_PEAK_TOPS,
+                         "unit": "Tlane-op/s", "frac": ops / sec / 1e12 / VALU_PEAK_TOPS,
+                         "lane_ops_per_pair": 2 * D + 1,
+                         "mfma_f16_tflops": mfma_flops / sec / 1e12,
+                         "mfma_f16_frac": mfma_flops / sec / 1e12 / MFMA_F16_PEAK_TFLOPS,
+                         "dtype": "f32 (psi), f16 x2 (products), f32 (tiles), f64 (sums)"},
             "T_obs": T_obs, "p_value": float(np.count_nonzero(T_perm > T_obs)) / nperm,
             "paper_context": "one permutation at 1e6 events took ~30 min on NVIDIA M2070 / K40c (Sect. 6)"}
 

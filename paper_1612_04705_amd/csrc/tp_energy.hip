@@ -14,11 +14,19 @@
 // sum w_i psi_ij G_jc plus the transposed term sum_i G_ic (Psi_upper w_q)_i,
 // where (Psi_upper w_q) is column q of the same product.
 //
-// V = Psi G is a dense contraction over j, done by MFMA (v_mfma_f32_32x32x2f32):
-// each lane produces one psi per step (VALU: distance, exp2), the matrix core
-// multiplies the 32 x 2 psi tile by the 2 x 32 column tile.  j streams through
-// LDS in chunks; at each chunk end the float32 tile is reduced per column into
-// float64 partials, so float32 only ever sums 2 * JC terms.
+// V = Psi G is a dense contraction over j, done on the matrix cores in half
+// precision with float32 accumulation (v_mfma_f32_32x32x16_f16).  psi is
+// formed in float32 (VALU: distance, exp2), scaled by 2^14 (exact) and split
+// into two float16 terms hi = rtz(psi), lo = rtz(psi - hi): the difference is
+// exact in float32 and hi + lo is within 2^-20 (relative, from below) of the
+// float32 psi; the scale keeps both terms clear of the float16 subnormals for
+// every psi above 2^-17.  The 0/1 columns are exact in float16, so each product
+// is exact and only the float32 accumulation rounds.  A lane forms 8 psi per
+// step, for its row and 8 consecutive j; the matrix core multiplies the
+// 32 x 16 tile of hi (then lo) by the 16 x 32 column tile.  Columns are staged
+// in LDS transposed ([c][j], float16), so a lane's 8 values of one column are
+// one 16-byte read.  Every FL chunks the float32 tiles are reduced per column
+// into float64 partials, so float32 only sums 2 * FL * JC products.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -27,75 +35,39 @@
 namespace tpe {
 namespace {
 
-typedef float f16v __attribute__((ext_vector_type(16)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __fp16 hp2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int ROWS = 128;     // rows i per workgroup (4 waves x 32)
-constexpr int JC = 256;       // j per LDS chunk (one per thread when staging)
+constexpr int JC = 128;       // j per LDS chunk
+constexpr int KS = 16;        // j per matrix-core step
+constexpr int FL = 8;         // chunks per float32 -> float64 reduction
+constexpr int GPAD = 8;       // float16 padding per staged column (spreads LDS banks)
+constexpr float PSI_SCALE = 16384.0f;         // 2^14
+constexpr double PSI_UNSCALE = 1.0 / 16384.0;
 
 template <int NT>
 struct Smem {
     static constexpr int C = 32 * NT;
-    float ys[JC][MAXD];                 // staged coordinates of a j chunk (padded with zeros)
-    uint8_t gs[JC * C];                 // staged columns of the chunk
-    uint8_t gi[ROWS * C];               // columns of this block's rows
-    float rw[ROWS][8];                  // per row: weights G[i][q] (0..2), chunk (Psi_upper G)[i][q] (4..6)
+    float ys[MAXD][JC];                 // coordinates of the chunk, [d][j], scaled by yscale
+    uint16_t gs[C][JC + GPAD];          // columns of the chunk, [c][j], float16 0 or 1
+    uint8_t gi[ROWS * C];               // columns of this block's rows, [i][c]
+    float rw[ROWS][8];                  // per row: weights G[i][q] (0..2), (Psi_upper G)[i][q] (4..6)
     double red[C][1 + MAXR];            // workgroup totals
 };
 
-// psi products of one staged chunk into the float32 tiles: lane (col, h) forms
-// psi for row i (its yi) and local j = jj + h, the matrix core adds the 32 x 2
-// psi tile times the 2 x 32 column tile t.  MASK keeps only local j > rel
-// (rel = i - j0), needed only in the chunk that holds the diagonal.
-template <int NT, int DP, bool MASK>
-__device__ __forceinline__ void chunk_products(const Smem<NT> &sm, const float (&yi)[DP], int rel, f16v (&acc)[NT])
-{
-    typedef float f32x4 __attribute__((ext_vector_type(4)));
-    constexpr int C = 32 * NT;
-    const int lane = threadIdx.x & 63;
-    const int h = lane >> 5;
-    const int col = lane & 31;
-#pragma unroll 2
-    for (int jj = 0; jj < JC; jj += 2) {
-        const int jl = jj + h;
-        float yj[8];
-        const f32x4 ya = reinterpret_cast<const f32x4 *>(&sm.ys[jl][0])[0];
-        yj[0] = ya.x; yj[1] = ya.y; yj[2] = ya.z; yj[3] = ya.w;
-        if (DP > 4) {
-            const f32x4 yb = reinterpret_cast<const f32x4 *>(&sm.ys[jl][0])[1];
-            yj[4] = yb.x; yj[5] = yb.y; yj[6] = yb.z; yj[7] = yb.w;
-        }
-        float d2 = 0.0f;
-#pragma unroll
-        for (int d = 0; d < DP; ++d) {
-            const float df = yi[d] - yj[d];
-            d2 = fmaf(df, df, d2);
-        }
-        float psi = __builtin_amdgcn_exp2f(-d2);
-        if (MASK) psi = (jl > rel) ? psi : 0.0f;
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const float b = (float)sm.gs[jl * C + 32 * t + col];
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(psi, b, acc[t], 0, 0, 0);
-        }
-    }
-}
-
-// One block of ROWS rows i against every j > i (upper triangle).  Coordinates
-// enter scaled by yscale, so that psi = 2^-(scaled distance)^2.
+// Row block setup: columns and row weights of rows ib .. ib + ROWS - 1, and
+// this lane's row coordinates (scaled by yscale, so psi = 2^-(scaled distance)^2).
 template <int NT, int DP>
-__device__ __forceinline__ void pair_block(const EParams &p, Smem<NT> &sm, int64_t ib, double (&part)[NT][1 + MAXR])
+__device__ __forceinline__ void setup_rows(const EParams &p, Smem<NT> &sm, int64_t ib, float (&yi)[DP])
 {
-    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-    typedef float f32x4 __attribute__((ext_vector_type(4)));
     constexpr int C = 32 * NT;
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int h = lane >> 5;
-    const int col = lane & 31;
-    const int64_t i = ib + wave * 32 + col;     // the row whose psi this lane computes
-    const int R = p.R;
-
+    const int64_t i = ib + (tid >> 6) * 32 + (tid & 31);
     __syncthreads();
     for (int e = tid; e < ROWS * C / 16; e += 256) {
         const int64_t r = ib + (e * 16) / C;
@@ -107,84 +79,170 @@ __device__ __forceinline__ void pair_block(const EParams &p, Smem<NT> &sm, int64
         const int64_t r = ib + tid;
 #pragma unroll
         for (int q = 0; q < MAXR; ++q)
-            sm.rw[tid][q] = (q < R && r < p.n) ? (float)p.G[r * C + q] : 0.0f;
+            sm.rw[tid][q] = (q < p.R && r < p.n) ? (float)p.G[r * C + q] : 0.0f;
 #pragma unroll
         for (int q = 3; q < 8; ++q) sm.rw[tid][q] = 0.0f;
     }
-    float yi[DP];
 #pragma unroll
     for (int d = 0; d < DP; ++d) yi[d] = (d < p.D && i < p.n) ? p.Y[d * p.ldY + i] * p.yscale : 0.0f;
+}
 
-    const int64_t jfirst = ib - ib % JC;        // the chunk that holds the diagonal
-    for (int64_t j0 = jfirst; j0 < p.n; j0 += JC) {
-        __syncthreads();
-        {   // coordinates: one j per thread (JC == 256 threads), padded with zeros
-            const int64_t j = j0 + tid;
-            float v[8];
+// Stage chunk j0 .. j0 + JC - 1: coordinates [d][j], and the columns transposed
+// to [c][j] as float16.  Each item takes 4 rows x 16 columns (four 16-byte
+// loads) and writes, per column, the 4 rows as one 8-byte word: bytes b of two
+// rows are placed as the 16-bit lanes of one word (b0 | b1 << 16), and the
+// 24-bit multiply by 0x3C00 turns each lane's 0/1 into float16 0 or 1.0.
+template <int NT, int DP>
+__device__ __forceinline__ void stage_chunk(const EParams &p, Smem<NT> &sm, int64_t j0)
+{
+    constexpr int C = 32 * NT;
+    constexpr int CG = C / 16;
+    constexpr int ITEMS = (JC / 4) * CG;
+    const int tid = threadIdx.x;
+    if (tid < JC) {
+        const int64_t j = j0 + tid;
 #pragma unroll
-            for (int d = 0; d < 8; ++d) v[d] = (d < p.D && j < p.n) ? p.Y[d * p.ldY + j] * p.yscale : 0.0f;
-            reinterpret_cast<f32x4 *>(&sm.ys[tid][0])[0] = f32x4{ v[0], v[1], v[2], v[3] };
-            reinterpret_cast<f32x4 *>(&sm.ys[tid][0])[1] = f32x4{ v[4], v[5], v[6], v[7] };
-        }
-        // columns: 16-byte loads of whole rows (C is a multiple of 32, rows 16-byte aligned)
-        for (int e = tid; e < JC * C / 16; e += 256) {
-            const int64_t j = j0 + (e * 16) / C;
-            u32x4 w = u32x4{ 0u, 0u, 0u, 0u };
-            if (j < p.n) w = reinterpret_cast<const u32x4 *>(p.G + j0 * C)[e];
-            reinterpret_cast<u32x4 *>(sm.gs)[e] = w;
-        }
-        __syncthreads();
-        f16v acc[NT];
+        for (int d = 0; d < DP; ++d) sm.ys[d][tid] = (d < p.D && j < p.n) ? p.Y[d * p.ldY + j] * p.yscale : 0.0f;
+    }
+    for (int it = tid; it < ITEMS; it += 256) {
+        const int jq = (it % (JC / 4)) * 4;
+        const int cg = it / (JC / 4);
+        u32x4 w[4];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = f16v{};
-        // rows beyond n carry zero weights and j beyond n zero columns: only j <= i needs a mask
-        if (j0 == jfirst) chunk_products<NT, DP, true>(sm, yi, (int)(i - j0), acc);
-        else chunk_products<NT, DP, false>(sm, yi, 0, acc);
-        // Reduce the chunk.  Lane (col, h) holds column 32 t + col for rows
-        // 8 (r / 4) + 4 h + r % 4 of this wave's 32.  The leading R columns are
-        // the row weights; their values (Psi_upper w_q)_i go through LDS so that
-        // every column can take the transposed term sum_i G_ic (Psi_upper w_q)_i.
-        if (col < R) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) sm.rw[wave * 32 + 8 * (r >> 2) + 4 * h + (r & 3)][4 + col] = acc[0][r];
-        }
-        __syncthreads();
-        float s0[NT], s1[NT], s2[NT], s3[NT];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) s0[t] = s1[t] = s2[t] = s3[t] = 0.0f;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row = wave * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-            const f32x4 wq = reinterpret_cast<const f32x4 *>(&sm.rw[row][0])[0];
-            const f32x4 vq = reinterpret_cast<const f32x4 *>(&sm.rw[row][0])[1];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const float v = acc[t][r];
-                const float g = (float)sm.gi[row * C + 32 * t + col];
-                s0[t] = fmaf(g, v, s0[t]);
-                s1[t] = fmaf(wq.x, v, fmaf(g, vq.x, s1[t]));
-                s2[t] = fmaf(wq.y, v, fmaf(g, vq.y, s2[t]));
-                s3[t] = fmaf(wq.z, v, fmaf(g, vq.z, s3[t]));
-            }
+        for (int rr = 0; rr < 4; ++rr) {
+            const int64_t j = j0 + jq + rr;
+            w[rr] = j < p.n ? *reinterpret_cast<const u32x4 *>(p.G + j * C + 16 * cg) : u32x4{ 0u, 0u, 0u, 0u };
         }
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            part[t][0] += 2.0 * (double)s0[t];       // diagonal-type sums are symmetric
-            part[t][1] += (double)s1[t];
-            part[t][2] += (double)s2[t];
-            part[t][3] += (double)s3[t];
+        for (int q = 0; q < 16; ++q) {
+            const int m = q & 3, wd = q >> 2;
+            // byte m of the second source (first row of the pair) to bits 0..7,
+            // byte m of the first source (second row) to bits 16..23, zeros elsewhere
+            const uint32_t sel = (uint32_t)m | (0x0cu << 8) | ((uint32_t)(4 + m) << 16) | (0x0cu << 24);
+            const uint32_t x01 = __builtin_amdgcn_perm(w[1][wd], w[0][wd], sel);
+            const uint32_t x23 = __builtin_amdgcn_perm(w[3][wd], w[2][wd], sel);
+            *reinterpret_cast<u32x2 *>(&sm.gs[16 * cg + q][jq]) = u32x2{ (uint32_t)__umul24(x01, 0x3C00u), (uint32_t)__umul24(x23, 0x3C00u) };
         }
     }
 }
 
-// Workgroup g takes row blocks g and nb - 1 - g: together about n pairs per row.
-template <int NT, int DP>
-__global__ __launch_bounds__(256) void tp_pairsum_kernel(const EParams p)
+// psi products of one staged chunk into the float32 tiles.  Lane (col, h) forms
+// psi for its row i (yi) and local j = jb + 8 h + q, q < 8; MASK keeps only
+// j > rel (rel = i - j0), needed only in the chunk that holds the diagonal.
+template <int NT, int DP, bool MASK>
+__device__ __forceinline__ void chunk_products(const Smem<NT> &sm, const float (&yi)[DP], int rel, f32x16 (&acc)[NT])
+{
+    const int lane = threadIdx.x & 63;
+    const int h = lane >> 5;
+    const int col = lane & 31;
+#pragma unroll 2
+    for (int jb = 0; jb < JC; jb += KS) {
+        const int jl = jb + 8 * h;
+        float ps[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) ps[q] = 0.0f;
+#pragma unroll
+        for (int d = 0; d < DP; ++d) {
+            const f32x4 ya = *reinterpret_cast<const f32x4 *>(&sm.ys[d][jl]);
+            const f32x4 yb = *reinterpret_cast<const f32x4 *>(&sm.ys[d][jl + 4]);
+            const float yj[8] = { ya.x, ya.y, ya.z, ya.w, yb.x, yb.y, yb.z, yb.w };
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const float df = yi[d] - yj[q];
+                ps[q] = fmaf(df, df, ps[q]);
+            }
+        }
+        u32x4 ah, al;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            float a = __builtin_amdgcn_exp2f(-ps[2 * k]) * PSI_SCALE;
+            float b = __builtin_amdgcn_exp2f(-ps[2 * k + 1]) * PSI_SCALE;
+            if (MASK) {
+                a = (jl + 2 * k > rel) ? a : 0.0f;
+                b = (jl + 2 * k + 1 > rel) ? b : 0.0f;
+            }
+            const uint32_t hw = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(a, b));
+            // residuals a - hi_a, b - hi_b, each one mixed-precision multiply-add
+            // reading its float16 half of hw directly (exact: hi is a truncation of a)
+            float ra, rb;
+            asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(ra) : "v"(hw), "v"(a));
+            asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(rb) : "v"(hw), "v"(b));
+            ah[k] = hw;
+            al[k] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(ra, rb));
+        }
+        const f16x8 A_hi = __builtin_bit_cast(f16x8, ah);
+        const f16x8 A_lo = __builtin_bit_cast(f16x8, al);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const f16x8 B = *reinterpret_cast<const f16x8 *>(&sm.gs[32 * t + col][jl]);
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A_hi, B, acc[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A_lo, B, acc[t], 0, 0, 0);
+        }
+    }
+}
+
+// Reduce the float32 tiles into the float64 partials and clear them.  Lane
+// (col, h) holds column 32 t + col for rows 8 (r / 4) + 4 h + r % 4 of its
+// wave's 32.  The leading R columns are the row weights; their values
+// (Psi_upper w_q)_i go through LDS so that every column can take the
+// transposed term sum_i G_ic (Psi_upper w_q)_i.
+template <int NT, int RR>
+__device__ __forceinline__ void flush(const EParams &p, Smem<NT> &sm, f32x16 (&acc)[NT], double (&part)[NT][1 + MAXR])
+{
+    constexpr int C = 32 * NT;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int h = lane >> 5;
+    const int col = lane & 31;
+    if (col < p.R) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) sm.rw[wave * 32 + 8 * (r >> 2) + 4 * h + (r & 3)][4 + col] = acc[0][r];
+    }
+    __syncthreads();
+    float s0[NT], s1[NT], s2[NT], s3[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) s0[t] = s1[t] = s2[t] = s3[t] = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int row = wave * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        const f32x4 wq = reinterpret_cast<const f32x4 *>(&sm.rw[row][0])[0];
+        const f32x4 vq = reinterpret_cast<const f32x4 *>(&sm.rw[row][0])[1];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const float v = acc[t][r];
+            const float g = (float)sm.gi[row * C + 32 * t + col];
+            s0[t] = fmaf(g, v, s0[t]);
+            s1[t] = fmaf(wq.x, v, fmaf(g, vq.x, s1[t]));
+            if (RR > 1) {
+                s2[t] = fmaf(wq.y, v, fmaf(g, vq.y, s2[t]));
+                s3[t] = fmaf(wq.z, v, fmaf(g, vq.z, s3[t]));
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        part[t][0] += 2.0 * (double)s0[t];       // diagonal-type sums are symmetric
+        part[t][1] += (double)s1[t];
+        part[t][2] += (double)s2[t];
+        part[t][3] += (double)s3[t];
+        acc[t] = f32x16{};
+    }
+}
+
+// Work split.  Row blocks g and nb - 1 - g pair up (together about n pairs per
+// row); their chunks, block g's first, form one list that K workgroups share in
+// equal contiguous pieces, so the launch has enough equal-sized workgroups to
+// keep every compute unit busy to the end.
+// RR: row-weight columns the reduction carries (1 covers R <= 1, 3 covers R <= 3).
+template <int NT, int DP, int RR>
+__global__ __launch_bounds__(256) void tp_pairsum_kernel(const EParams p, const int K)
 {
     constexpr int C = 32 * NT;
     __shared__ __align__(16) Smem<NT> sm;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
+    const int wave = tid >> 6;
     const int h = lane >> 5;
     const int col = lane & 31;
     const int64_t nb = (p.n + ROWS - 1) / ROWS;
@@ -194,43 +252,89 @@ __global__ __launch_bounds__(256) void tp_pairsum_kernel(const EParams p)
     for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int q = 0; q <= MAXR; ++q) part[t][q] = 0.0;
-    const int64_t b1 = blockIdx.x, b2 = nb - 1 - (int64_t)blockIdx.x;
-    for (int k = 0; k < (b2 > b1 ? 2 : 1); ++k) pair_block<NT, DP>(p, sm, (k == 0 ? b1 : b2) * ROWS, part);
+    f32x16 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f32x16{};
+
+    const int64_t g = blockIdx.x / K, k = blockIdx.x % K;
+    const int64_t b1 = g, b2 = nb - 1 - g;
+    // ROWS == JC: a row block starts a chunk, and its first chunk holds the diagonal
+    const int64_t L1 = (p.n - b1 * ROWS + JC - 1) / JC;
+    const int64_t L2 = b2 > b1 ? (p.n - b2 * ROWS + JC - 1) / JC : 0;
+    const int64_t L = L1 + L2;
+    const int64_t v0 = k * L / K, v1 = (k + 1) * L / K;
+    float yi[DP];
+    int64_t cur = -1;
+    int since = 0;
+    for (int64_t v = v0; v < v1; ++v) {
+        const int64_t blk = v < L1 ? b1 : b2;
+        const int64_t c0 = v < L1 ? v : v - L1;      // chunk within the block's row
+        const int64_t j0 = blk * ROWS + c0 * JC;
+        if (blk != cur) {
+            setup_rows<NT, DP>(p, sm, blk * ROWS, yi);
+            cur = blk;
+        }
+        __syncthreads();
+        stage_chunk<NT, DP>(p, sm, j0);
+        __syncthreads();
+        if (c0 == 0) chunk_products<NT, DP, true>(sm, yi, wave * 32 + col, acc);
+        else chunk_products<NT, DP, false>(sm, yi, 0, acc);
+        const bool block_ends = v + 1 == v1 || v + 1 == L1;
+        if (++since == FL || block_ends) {
+            flush<NT, RR>(p, sm, acc, part);
+            since = 0;
+        }
+    }
     // combine the two row halves of each column, then the four waves, then workgroups
     const int R = p.R;
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int q = 0; q <= MAXR; ++q) {
-            double v = part[t][q];
-            v += __shfl_xor(v, 32);
-            if (h == 0 && q <= R) atomicAdd(&sm.red[32 * t + col][q], v);
+            double x = part[t][q];
+            x += __shfl_xor(x, 32);
+            if (h == 0 && q <= R) atomicAdd(&sm.red[32 * t + col][q], x);
         }
     __syncthreads();
-    for (int e = tid; e < C * (1 + R); e += 256) {
-        const int c = e / (1 + R), q = e % (1 + R);
-        if (c < p.C) atomicAdd(&p.sums[(int64_t)c * (1 + R) + q], sm.red[c][q]);
-    }
+    if (v1 > v0)
+        for (int e = tid; e < C * (1 + R); e += 256) {
+            const int c = e / (1 + R), q = e % (1 + R);
+            if (c < p.C) atomicAdd(&p.sums[(int64_t)c * (1 + R) + q], sm.red[c][q] * PSI_UNSCALE);
+        }
 }
 
-template <int NT, int DP>
+template <int NT, int DP, int RR>
 void launch_ntd(const EParams &p, hipStream_t st)
 {
     const int64_t nb = (p.n + ROWS - 1) / ROWS;
-    const int64_t grid = (nb + 1) / 2;
-    hipLaunchKernelGGL((tp_pairsum_kernel<NT, DP>), dim3((unsigned)grid), dim3(256), 0, st, p);
+    const int64_t pairs = (nb + 1) / 2;
+    // pieces per block pair: about 64 workgroups per compute unit in all (the
+    // last partial wave of workgroups then costs a few percent), no piece
+    // shorter than two chunks
+    const int64_t chunks = (p.n + JC - 1) / JC;
+    int64_t K = (16384 + pairs - 1) / pairs;
+    K = K > chunks / 2 ? chunks / 2 : K;
+    K = K < 1 ? 1 : K;
+    hipLaunchKernelGGL((tp_pairsum_kernel<NT, DP, RR>), dim3((unsigned)(pairs * K)), dim3(256), 0, st, p, (int)K);
+}
+
+template <int NT, int RR>
+void launch_ntr(const EParams &p, hipStream_t st)
+{
+    switch (p.D) {   // coordinates per event, padded up to the next instantiated count
+    case 1: case 2: launch_ntd<NT, 2, RR>(p, st); break;
+    case 3: case 4: launch_ntd<NT, 4, RR>(p, st); break;
+    case 5: launch_ntd<NT, 5, RR>(p, st); break;
+    case 6: launch_ntd<NT, 6, RR>(p, st); break;
+    default: launch_ntd<NT, 8, RR>(p, st); break;
+    }
 }
 
 template <int NT>
 void launch_nt(const EParams &p, hipStream_t st)
 {
-    switch (p.D) {   // coordinates per event, padded up to the next instantiated count
-    case 1: case 2: launch_ntd<NT, 2>(p, st); break;
-    case 3: case 4: launch_ntd<NT, 4>(p, st); break;
-    case 5: launch_ntd<NT, 5>(p, st); break;
-    case 6: launch_ntd<NT, 6>(p, st); break;
-    default: launch_ntd<NT, 8>(p, st); break;
-    }
+    if (p.R <= 1) launch_ntr<NT, 1>(p, st);
+    else launch_ntr<NT, 3>(p, st);
 }
 
 // Invariant mass of the slots in a mask, per event (Sect. 4 coordinates).

@@ -1,12 +1,14 @@
 """GPU parity of the energy test (pair sums on the matrix cores) against the oracle.
 
 Tolerance.  The device forms coordinates in float32 (relative rounding 2^-24 of
-masses ~1-2 GeV), psi in float32 with the hardware exp2 (a few ulp), and sums
-each chunk of 2 x 256 products in float32 before float64 accumulation.  Each
-psi is therefore within ~1e-6 relative of the float64 value (the distance
-error d * |delta d| / sigma^2 with |delta d| <~ 4e-7 GeV dominates at
-sigma = 0.3 GeV), and so is each of the three terms of T.  The test allows
-1e-5 of the sum of the three terms' magnitudes.
+masses ~1-2 GeV) and psi in float32 with the hardware exp2 (a few ulp): the
+distance error d * |delta d| / sigma^2 with |delta d| <~ 4e-7 GeV puts each psi
+within ~1e-6 (relative) of the float64 value at sigma = 0.3 GeV.  The matrix
+cores take psi as two float16 terms whose sum is within 2^-20 (~1e-6) of it,
+and accumulate exact products in float32 tiles that are reduced into float64
+every 1024 j: 128 accumulation roundings of 2^-24 (worst case ~8e-6, typically
+~3e-7 as they are of random sign).  Each of the three terms of T inherits these
+relative errors; the test allows 1e-5 of the sum of the three terms' magnitudes.
 """
 import numpy as np
 import pytest
