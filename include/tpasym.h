@@ -82,10 +82,23 @@ typedef struct {
  * triple = (A, B, C): C_T = p_A . (p_B x p_C) in the M rest frame; the three
  * slots must be distinct.  planes = (i, j, k, l), a permutation of 0..3: the
  * acoplanarity angle Phi is the angle between the (i, j) and (k, l) planes
- * in the M rest frame (Sect. 5: a triple-product-type, P-odd coordinate). */
+ * in the M rest frame (Sect. 5: a triple-product-type, P-odd coordinate).
+ *
+ * identical = (f, s): two slots holding identical particles (two pi- in
+ * Lambda_b -> p pi- pi+ pi-, two K- in Lambda_b -> p K- K+ K-), or (-1, -1).
+ * Swapping them flips the sign of C_T, so their order is part of the
+ * definition: the pass puts the one with the larger energy in the M rest frame
+ * (the larger P.p) in slot f and the other in slot s, whatever the stored
+ * order, so unordered data can be fed as is.  The comparison is certified
+ * like every other decision (float64 with an error bound, exact arithmetic
+ * when that does not settle it); an exact tie keeps the stored order.  When a
+ * plane angle is binned, f and s must lie in different planes with matching
+ * positions up to the pair swap: {planes[0], planes[2]} or {planes[1],
+ * planes[3]} (TP_EUNSUPPORTED otherwise). */
 typedef struct {
     int32_t triple[3];
     int32_t planes[4];
+    int32_t identical[2];
 } tp_channel;
 
 typedef enum {
@@ -252,11 +265,11 @@ const char *tp_strerror(int status);
 int tp_version(void);
 
 /* ------------------------------------------------------------------------
- * Energy test (Sect. 2.2, eq. (2); background-subtracted form Sect. 4, eq. (3))
+ * Energy test (Sect. 2.2, eq. (2); background-subtracted form Sect. 3, eq. (3))
  *
  * The statistic compares two samples through psi_ij = exp(-d_ij^2 / 2 sigma^2),
  * d_ij the Euclidean distance between events in phase-space coordinates
- * (invariant masses, Sect. 4 Table 1).  The device computes, for a 0/1 column
+ * (invariant masses, Sect. 4.2 Table 1).  The device computes, for a 0/1 column
  * matrix G [n][ncols] (one column per sample indicator: the observed split,
  * each permutation of it, ...) whose leading ``nrow`` columns double as row
  * weights, the pair sums

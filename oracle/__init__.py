@@ -50,7 +50,7 @@ def _load():
         lib.or_pass.restype = ctypes.c_int64
         lib.or_pass.argtypes = [
             ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p,
-            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p,
             ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_void_p),
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
@@ -81,7 +81,7 @@ def _event_comps(arr, i):
     return [[float(arr[s][c][i]) for c in range(4)] for s in range(4)]
 
 
-def _pass(arr, tag, triple, planes, ax, nthreads, want_events, cap):
+def _pass(arr, tag, triple, planes, ax, nthreads, want_events, cap, identical=None):
     lib = _load()
     n = tag.shape[0]
     nb_total = int(np.prod([len(e) - 1 for _, _, e in ax])) if ax else 0
@@ -97,9 +97,11 @@ def _pass(arr, tag, triple, planes, ax, nthreads, want_events, cap):
     slots = (ctypes.c_int32 * 2)(*([s for _, s, _ in ax] + [0, 0])[:2])
     edge_arrs = [np.ascontiguousarray(e) for _, _, e in ax]
     eptr = (ctypes.c_void_p * 2)(*([e.ctypes.data for e in edge_arrs] + [None, None])[:2])
+    ident = (ctypes.c_int32 * 2)(*identical) if identical is not None else None
     t0 = time.perf_counter()
     nflag = lib.or_pass(n, 0 if arr[0][0].dtype == np.float32 else 1, ptrs, tag.ctypes.data,
-                        (ctypes.c_int32 * 3)(*triple), (ctypes.c_int32 * 4)(*planes), len(ax),
+                        (ctypes.c_int32 * 3)(*triple), (ctypes.c_int32 * 4)(*planes),
+                        ctypes.cast(ident, ctypes.c_void_p) if ident is not None else None, len(ax),
                         kinds, nbins, slots, eptr, counts.ctypes.data, stats.ctypes.data,
                         flagged.ctypes.data, cap,
                         cls.ctypes.data if cls is not None else None,
@@ -112,7 +114,7 @@ def _pass(arr, tag, triple, planes, ax, nthreads, want_events, cap):
 
 
 def run(comps, tag, triple, planes, axes=(), nthreads: int = 0, want_events: bool = False,
-        resolve: bool = True):
+        resolve: bool = True, identical=None):
     """Counts and stats of a whole sample.
 
     Returns dict(counts=[(nbins+1) x 4] python ints (row 0 = all classified
@@ -121,13 +123,15 @@ def run(comps, tag, triple, planes, axes=(), nthreads: int = 0, want_events: boo
     want_events also per-event class (int8, flagged events after resolution)
     and the float64 C_T values and axis coordinates (cos Phi, m^2, |cos theta|).
     Flagged events keep their float64 coordinates but the resolved class.
+    ``identical`` = (fast slot, slow slot): two identical particles, ordered
+    per event by rest-frame energy before anything else.
     """
     arr, tag = _arrays(comps, tag)
     ax = _axes_tuple(axes)
     cap = max(1024, tag.shape[0] // 1000)
-    res = _pass(arr, tag, triple, planes, ax, nthreads, want_events, cap)
+    res = _pass(arr, tag, triple, planes, ax, nthreads, want_events, cap, identical)
     if res[4] > cap:
-        res = _pass(arr, tag, triple, planes, ax, nthreads, want_events, res[4] + 16)
+        res = _pass(arr, tag, triple, planes, ax, nthreads, want_events, res[4] + 16, identical)
     nb_total, counts, stats, flagged, nflag, cls, ct, seconds = res
     counts_l = [[int(v) for v in counts[r * 4:(r + 1) * 4]] for r in range(nb_total + 1)]
     stats_l = [int(v) for v in stats]
@@ -135,7 +139,7 @@ def run(comps, tag, triple, planes, axes=(), nthreads: int = 0, want_events: boo
     t1 = time.perf_counter()
     if resolve:
         for i in fl:
-            c, b = exact.exact_decision(_event_comps(arr, i), int(tag[i]), triple, planes, ax)
+            c, b = exact.exact_decision(_event_comps(arr, i), int(tag[i]), triple, planes, ax, identical)
             exact.accumulate(counts_l, stats_l, c, b if ax else None)
             if cls is not None:
                 cls[i] = c
@@ -147,7 +151,7 @@ def run(comps, tag, triple, planes, axes=(), nthreads: int = 0, want_events: boo
     return out
 
 
-def brute_force(comps, tag, triple, planes, axes=()):
+def brute_force(comps, tag, triple, planes, axes=(), identical=None):
     """Decide every event in exact rational arithmetic (small inputs only)."""
     arr, tag = _arrays(comps, tag)
     ax = _axes_tuple(axes)
@@ -156,7 +160,7 @@ def brute_force(comps, tag, triple, planes, axes=()):
     stats = [0, 0, 0, 0]
     cls = np.zeros(tag.shape[0], dtype=np.int8)
     for i in range(tag.shape[0]):
-        c, b = exact.exact_decision(_event_comps(arr, i), int(tag[i]), triple, planes, ax)
+        c, b = exact.exact_decision(_event_comps(arr, i), int(tag[i]), triple, planes, ax, identical)
         exact.accumulate(counts, stats, c, b if ax else None)
         cls[i] = c
     return dict(counts=counts, stats=stats, cls=cls)

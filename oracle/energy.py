@@ -3,9 +3,9 @@
 Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s CPU baseline may
 use this module.  It shares no code with the HIP path.
 
-Follows the paper's Sect. 2.2 (energy test) and Sect. 4 (background) directly:
+Follows the paper's Sect. 2.2 (energy test) and Sect. 3 (background) directly:
 
-* coordinates: invariant masses of particle combinations (Sect. 4, Table 1),
+* coordinates: invariant masses of particle combinations (Sect. 4.2, Table 1),
   computed from the stored four-vectors in float64;
 * psi_ij = exp(-d_ij^2 / (2 sigma^2)), d_ij the Euclidean distance between the
   coordinate vectors of events i and j (Sect. 2.2);

@@ -26,6 +26,8 @@ formulas of the float64 oracle, not by re-deriving them):
       Nn = (P.p_s) E_P - M^2 E_s,  A = G_ss,  B = E_P^2 - M^2 = |P_lab|^2,
   |cos theta| = |Nn| / sqrt(A B).
 * Invariant mass of a slot set S: m^2 = (sum_{s in S} p_s)^2.
+* Rest-frame energy: E*_s = (P.p_s) / M, so of two identical particles the
+  faster (larger E*) has the larger P.p_s.
 """
 from __future__ import annotations
 
@@ -166,11 +168,30 @@ class ExactEvent:
         return sum(1 for k in range(1, n) if cmp[k] >= 0)
 
 
-def exact_decision(comps, tag, triple, planes, axes):
+def order_identical(comps, identical):
+    """comps with the identical particles of slots (f, s) in canonical order:
+    the larger rest-frame energy in slot f; an exact tie keeps the stored order.
+    Events without a rest frame (or not finite) are returned unchanged."""
+    f, s = identical
+    if not all(math.isfinite(v) for row in comps for v in row):
+        return comps
+    q = [[F(v) for v in row] for row in comps]
+    P = [sum(q[k][c] for k in range(4)) for c in range(4)]
+    if not (P[0] > 0 and mdot(P, P) > 0):
+        return comps
+    if mdot(P, q[s]) > mdot(P, q[f]):
+        comps = [list(row) for row in comps]
+        comps[f], comps[s] = comps[s], comps[f]
+    return comps
+
+
+def exact_decision(comps, tag, triple, planes, axes, identical=None):
     """(class, combined bin or -1 out of range or None if not binned) of one event.
 
-    axes: list of (kind, slots, edges).
+    axes: list of (kind, slots, edges); identical: None or (fast slot, slow slot).
     """
+    if identical is not None:
+        comps = order_identical(comps, identical)
     ev = ExactEvent(comps, tag)
     c = ev.cls(triple)
     if c >= CLS_ZERO or not axes:

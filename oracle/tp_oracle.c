@@ -10,6 +10,9 @@
  *   1. read the stored components (float32 promoted exactly, or float64);
  *   2. P = sum of the four momenta, M^2 = P.P, M = sqrt(M^2);
  *   3. boost every daughter into the M rest frame (pure boost, beta = P/E_P);
+ *      if the channel has two identical particles (slots f, s), the one with
+ *      the larger rest-frame energy E* is put in slot f (an exact tie keeps
+ *      the stored order), since swapping them flips the sign of C_T;
  *   4. C_T = p*_A . (p*_B x p*_C) with the channel's slots (Sect. 5); for an
  *      anti-particle event the same slots hold the C-conjugates, giving Cbar_T;
  *   5. class by flavour and sign (eq. (4)): M with C_T>0 -> [I], C_T<0 -> [II];
@@ -94,10 +97,12 @@ static int64_t bin_increasing(double v, const double *e, int nb, double margin, 
     return j;
 }
 
-static or_event one_event(const double p[4][4], int tag, const int32_t triple[3],
-                          const int32_t planes[4], const or_binning *bn)
+static or_event one_event(const double pin[4][4], int tag, const int32_t triple[3],
+                          const int32_t planes[4], const int32_t *ident, const or_binning *bn)
 {
     or_event r = { OR_INVALID, -2, 0.0, { 0.0, 0.0 } };
+    double p[4][4];
+    memcpy(p, pin, sizeof p);
     for (int s = 0; s < 4; ++s)
         for (int c = 0; c < 4; ++c)
             if (!isfinite(p[s][c])) return r;
@@ -136,6 +141,22 @@ static or_event one_event(const double p[4][4], int tag, const int32_t triple[3]
         Es[s] = fabs(gamma * (q[0] - bp)) + norm3(ps[s]);
     }
     double g2 = 1.0 + gamma * gamma;
+
+    /* step 3b: identical particles ordered by rest-frame energy E* = gamma (E - beta.p) */
+    if (ident && ident[0] >= 0) {
+        const int f = ident[0], sl = ident[1];
+        const double Ef = gamma * (p[f][0] - (beta[0] * p[f][1] + beta[1] * p[f][2] + beta[2] * p[f][3]));
+        const double Esl = gamma * (p[sl][0] - (beta[0] * p[sl][1] + beta[1] * p[sl][2] + beta[2] * p[sl][3]));
+        if (fabs(Ef - Esl) <= OR_TAU * g2 * (Es[f] + Es[sl])) {
+            r.cls = OR_FLAGGED;
+            return r;
+        }
+        if (Esl > Ef) {
+            for (int c = 0; c < 4; ++c) { double t = p[f][c]; p[f][c] = p[sl][c]; p[sl][c] = t; }
+            for (int c = 0; c < 3; ++c) { double t = ps[f][c]; ps[f][c] = ps[sl][c]; ps[sl][c] = t; }
+            double t = Es[f]; Es[f] = Es[sl]; Es[sl] = t;
+        }
+    }
 
     /* step 4: triple product in the rest frame */
     double bc[3];
@@ -229,9 +250,10 @@ static or_event one_event(const double p[4][4], int tag, const int32_t triple[3]
  *            (may exceed cap: then only cap were written).
  *   cls_out (int8[n]), ct_out (double[n]) and coord_out (double[2n], axis values
  *   cos Phi / m^2 / |cos theta| of each event) may be NULL.
+ *   ident: NULL or int32[2] = (fast slot, slow slot) of two identical particles.
  */
 int64_t or_pass(int64_t n, int32_t dtype, const void *const *comp, const int8_t *tag,
-                const int32_t *triple, const int32_t *planes,
+                const int32_t *triple, const int32_t *planes, const int32_t *ident,
                 int32_t naxes, const int32_t *kind, const int32_t *nbins, const int32_t *slots,
                 const double *const *edges,
                 uint64_t *counts, uint64_t *stats, int64_t *flagged, int64_t cap,
@@ -265,7 +287,7 @@ int64_t or_pass(int64_t n, int32_t dtype, const void *const *comp, const int8_t 
                 for (int c = 0; c < 4; ++c)
                     p[s][c] = dtype == 0 ? (double)((const float *)comp[s * 4 + c])[i]
                                          : ((const double *)comp[s * 4 + c])[i];
-            or_event ev = one_event(p, tag[i], triple, planes, &bn);
+            or_event ev = one_event(p, tag[i], triple, planes, ident, &bn);
             if (cls_out) cls_out[i] = (int8_t)ev.cls;
             if (ct_out) ct_out[i] = ev.ct;
             if (coord_out) { coord_out[2 * i] = ev.coord[0]; coord_out[2 * i + 1] = ev.coord[1]; }

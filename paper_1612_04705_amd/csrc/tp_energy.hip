@@ -1,4 +1,4 @@
-// Energy-test pair sums on gfx950 (Sect. 2.2 eq. (2), Sect. 4 eq. (3)).
+// Energy-test pair sums on gfx950 (Sect. 2.2 eq. (2), Sect. 3 eq. (3)).
 //
 // For coordinates y_i (D <= 8 per event), psi_ij = exp(-|y_i - y_j|^2 / 2 sigma^2)
 // for i != j (0 on the diagonal) and a 0/1 column matrix G [n][C], the kernel
@@ -337,7 +337,7 @@ void launch_nt(const EParams &p, hipStream_t st)
     else launch_ntr<NT, 3>(p, st);
 }
 
-// Invariant mass of the slots in a mask, per event (Sect. 4 coordinates).
+// Invariant mass of the slots in a mask, per event (Sect. 4.2 coordinates).
 template <typename Tin>
 __global__ void tp_coords_kernel(CParams c)
 {

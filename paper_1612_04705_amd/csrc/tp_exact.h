@@ -340,6 +340,17 @@ TP_HD inline bool event_build(Event &ev, const int64_t mant[4][4], const int ex[
     return true;
 }
 
+// Exact sign of P.p_a - P.p_b (the rest-frame energy order of slots a and b,
+// M E*_s = P.p_s), or 2 if the event exceeds the arithmetic's capacity.
+TP_HD inline int order_sign(const int64_t mant[4][4], const int ex[4][4], int span, int a, int b)
+{
+    Event ev;
+    if (!event_build(ev, mant, ex, span)) return 2;
+    Big<L2> d;
+    ev.ok = ev.ok && big_addsub(d, ev.PP[a], ev.PP[b], -1);
+    return ev.ok ? big_sign(d) : 2;
+}
+
 // E_P > 0 and M^2 > 0
 TP_HD inline bool event_timelike(const Event &ev)
 {

@@ -39,8 +39,32 @@ __global__ __launch_bounds__(64) void tp_exact_kernel(const KParams kp)
         for (int a = 0; a < S.naxes && a < 2; ++a)
             eds[a] = kp.edges + S.eoff[a] + (S.kind[a] == AX_MASS ? 2 * (S.nbins[a] + 1) : 0);
         const int nax = MODE == 0 ? S.naxes : 0;
+        const int span = sizeof(Tin) == 4 ? 136 : 107;
+        // identical particles: exact rest-frame energy order first (an exact
+        // tie keeps the stored order), then every decision on the ordered rows
+        bool order_unres = false;
+        if (finite && S.olo >= 0) {
+            int64_t om[4][4];
+            int oe[4][4];
+            for (int k = 0; k < 4; ++k)
+                for (int c = 0; c < 4; ++c) {
+                    if constexpr (sizeof(Tin) == 4) tpx::decode_f32((float)xv[k][c], om[k][c], oe[k][c]);
+                    else tpx::decode_f64(xv[k][c], om[k][c], oe[k][c]);
+                }
+            const int sg = tpx::order_sign(om, oe, span, S.olo, S.olo + 2);
+            if (sg == 2) {
+                order_unres = true;
+            } else if (sg * S.odir < 0) {
+                for (int c = 0; c < 4; ++c) {
+                    const double t = xv[S.olo][c];
+                    xv[S.olo][c] = xv[S.olo + 2][c];
+                    xv[S.olo + 2][c] = t;
+                }
+            }
+        }
         int bin = -1;
-        int cls = finite ? tpw::decide_dw(xv, tag, S.sigma, nax, S.kind, S.nbins, S.slots, eds, bin)
+        int cls = order_unres ? (int)CLS_UNRESOLVED
+                : finite ? tpw::decide_dw(xv, tag, S.sigma, nax, S.kind, S.nbins, S.slots, eds, bin)
                          : (int)tpw::W_UNCERTAIN;
         if (cls == tpw::W_UNCERTAIN) {
             int64_t mant[4][4];
@@ -50,7 +74,7 @@ __global__ __launch_bounds__(64) void tp_exact_kernel(const KParams kp)
                     if constexpr (sizeof(Tin) == 4) tpx::decode_f32((float)xv[k][c], mant[k][c], ex[k][c]);
                     else tpx::decode_f64(xv[k][c], mant[k][c], ex[k][c]);
                 }
-            cls = tpx::decide(mant, ex, finite, tag, sizeof(Tin) == 4 ? 136 : 107, S.sigma, nax, S.kind,
+            cls = tpx::decide(mant, ex, finite, tag, span, S.sigma, nax, S.kind,
                               S.nbins, S.slots, eds, bin);
         }
         const bool unres = cls == CLS_UNRESOLVED;

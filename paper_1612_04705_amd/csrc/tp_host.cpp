@@ -201,6 +201,37 @@ int check_channel(const tp_channel *ch)
         seen |= 1 << ch->planes[k];
     }
     if (seen != 15) return fail(TP_EINVAL, "planes must be a permutation of 0..3");
+    const int f = ch->identical[0], sl = ch->identical[1];
+    if (!(f == -1 && sl == -1)) {
+        if (f < 0 || f > 3 || sl < 0 || sl > 3 || f == sl)
+            return fail(TP_EINVAL, "identical slots must be two distinct slots of 0..3, or both -1");
+    }
+    return TP_OK;
+}
+
+bool has_axis(const tp_binning *bn, int kind)
+{
+    if (bn)
+        for (int a = 0; a < bn->naxes; ++a)
+            if (bn->axis[a].kind == kind) return true;
+    return false;
+}
+
+// Identical particles need kernel slots {0, 2} or {1, 3} (positions of planes
+// up to the XOR relabelling).  With a plane angle binned the planes fix the
+// order; without one any order serves, and the pair is placed at positions 1, 3.
+int check_identical(const tp_channel *ch, const tp_binning *bn)
+{
+    const int f = ch->identical[0], sl = ch->identical[1];
+    if (f < 0 || !has_axis(bn, TP_AXIS_ABSPHI)) return TP_OK;
+    int pf = 0, ps = 0;
+    for (int t = 0; t < 4; ++t) {
+        if (ch->planes[t] == f) pf = t;
+        if (ch->planes[t] == sl) ps = t;
+    }
+    if ((pf ^ ps) != 2)
+        return fail(TP_EUNSUPPORTED, "with a plane angle binned, the identical slots must sit at positions "
+                                     "(0, 2) or (1, 3) of planes");
     return TP_OK;
 }
 
@@ -276,6 +307,20 @@ void fill_sample(KSample &k, const tp_events &ev, const tp_channel &ch, const tp
                  std::vector<double> &edges)
 {
     std::memset(&k, 0, sizeof k);
+    // Identical particles without a binned plane angle: any kernel order is
+    // valid (sigma follows it), so the planes are replaced by an order that
+    // puts the pair at positions 1 and 3.
+    int planes[4] = { ch.planes[0], ch.planes[1], ch.planes[2], ch.planes[3] };
+    const int idf = ch.identical[0], ids = ch.identical[1];
+    if (idf >= 0 && !has_axis(bn, TP_AXIS_ABSPHI)) {
+        int o[2], no = 0;
+        for (int s = 0; s < 4; ++s)
+            if (s != idf && s != ids) o[no++] = s;
+        planes[0] = o[0];
+        planes[1] = idf;
+        planes[2] = o[1];
+        planes[3] = ids;
+    }
     // Kernel order: kernel slot t holds channel slot planes[t ^ r].  The XOR
     // relabelling t -> t ^ r is the identity or a product of two transpositions
     // ((01)(23), (02)(13), (03)(12)): an even permutation that maps the plane
@@ -288,16 +333,16 @@ void fill_sample(KSample &k, const tp_events &ev, const tp_channel &ch, const tp
         for (int a = 0; a < bn->naxes; ++a)
             if (bn->axis[a].kind == TP_AXIS_ABSCOS) {
                 for (int t = 0; t < 4; ++t)
-                    if (ch.planes[t] == bn->axis[a].slots) r = t;
+                    if (planes[t] == bn->axis[a].slots) r = t;
                 break;
             }
     int inv[4];
-    for (int t = 0; t < 4; ++t) inv[ch.planes[t ^ r]] = t;   // channel slot -> kernel slot
+    for (int t = 0; t < 4; ++t) inv[planes[t ^ r]] = t;   // channel slot -> kernel slot
     bool vec = true;
     for (int t = 0; t < 4; ++t)
         for (int c = 0; c < 4; ++c) {
-            k.p[t * 4 + c] = ev.p[ch.planes[t ^ r]][c];
-            vec = vec && aligned16(ev.p[ch.planes[t ^ r]][c]);
+            k.p[t * 4 + c] = ev.p[planes[t ^ r]][c];
+            vec = vec && aligned16(ev.p[planes[t ^ r]][c]);
         }
     k.tag = ev.tag;
     vec = vec && ((reinterpret_cast<uintptr_t>(ev.tag) & 3u) == 0);
@@ -311,7 +356,15 @@ void fill_sample(KSample &k, const tp_events &ev, const tp_channel &ch, const tp
     //        det[kernel rows] = sgn(planes) det[p0..p3] (the relabelling is even)
     int D = 0 + 1 + 2 + 3 - ch.triple[0] - ch.triple[1] - ch.triple[2];
     int dabc[4] = { D, ch.triple[0], ch.triple[1], ch.triple[2] };
-    k.sigma = perm_sign(dabc, 4) * perm_sign(ch.planes, 4);
+    k.sigma = perm_sign(dabc, 4) * perm_sign(planes, 4);
+    // identical pair: kernel slots inv[f], inv[s] are {0, 2} or {1, 3}
+    k.olo = -1;
+    k.odir = 1;
+    if (idf >= 0) {
+        const int kf = inv[idf], ks = inv[ids];
+        k.olo = kf < ks ? kf : ks;
+        k.odir = kf == k.olo ? 1 : -1;
+    }
     k.naxes = bn ? bn->naxes : 0;
     k.kind[0] = k.kind[1] = AX_NONE;
     k.nbtot = 0;
@@ -549,10 +602,10 @@ int launch_plan(Device &d, const Plan &p, const std::vector<tp_tuning> &gtu, int
         const uint32_t m = std::min<uint32_t>(cnt, 4096);
         std::vector<uint64_t> lst(m);
         if (m) TP_HIP(hipMemcpy(lst.data(), ws.xlist, m * sizeof(uint64_t), hipMemcpyDeviceToHost));
-        int why[5] = { 0, 0, 0, 0, 0 };
-        for (uint64_t e : lst) why[std::min<int>(4, (int)(e >> 60))]++;
-        std::fprintf(stderr, "tp_debug: %u deferred (validity %d, sign %d, axis0 %d, axis1 %d)", cnt, why[1],
-                     why[2], why[3], why[4]);
+        int why[6] = { 0, 0, 0, 0, 0, 0 };
+        for (uint64_t e : lst) why[std::min<int>(5, (int)(e >> 60))]++;
+        std::fprintf(stderr, "tp_debug: %u deferred (validity %d, sign %d, axis0 %d, axis1 %d, order %d)", cnt,
+                     why[1], why[2], why[3], why[4], why[5]);
         for (uint32_t k = 0; k < std::min<uint32_t>(m, 8); ++k)
             std::fprintf(stderr, " [s%d e%lld w%d]", (int)((lst[k] >> 40) & 0xfffff),
                          (long long)(lst[k] & ((1ull << 40) - 1)), (int)(lst[k] >> 60));
@@ -812,6 +865,8 @@ int tp_bin(const tp_events *ev, const tp_channel *ch, const tp_binning *bn, int3
     if (rc) return rc;
     rc = check_binning(bn);
     if (rc) return rc;
+    rc = check_identical(ch, bn);
+    if (rc) return rc;
     if (!counts || !stats) return fail(TP_EINVAL, "counts and stats are required");
     if (ev->n == 0) return TP_OK;
     std::vector<Req> rq{ Req{ ev, ch, bn, counts, stats, nullptr, nullptr } };
@@ -833,6 +888,8 @@ int tp_batch(const tp_sample *samples, int32_t nsamples, int32_t precision, cons
         rc = check_channel(&s.ch);
         if (rc) return rc;
         rc = check_binning(&s.bn);
+        if (rc) return rc;
+        rc = check_identical(&s.ch, &s.bn);
         if (rc) return rc;
         if (!s.counts || !s.stats) return fail(TP_EINVAL, "counts and stats are required");
         if (dtype >= 0 && s.ev.dtype != dtype) return fail(TP_EUNSUPPORTED, "all samples of a batch share one dtype");
@@ -856,6 +913,8 @@ int tp_autotune(const tp_sample *samples, int32_t nsamples, int32_t precision, v
         rc = check_channel(&samples[i].ch);
         if (rc) return rc;
         rc = check_binning(&samples[i].bn);
+        if (rc) return rc;
+        rc = check_identical(&samples[i].ch, &samples[i].bn);
         if (rc) return rc;
         int tot = 1;
         for (int a = 0; a < samples[i].bn.naxes; ++a) tot *= samples[i].bn.axis[a].nbins;

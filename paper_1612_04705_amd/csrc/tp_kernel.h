@@ -35,6 +35,8 @@ struct KSample {
     int32_t vec;              // 1: all arrays 16-byte aligned (vector loads allowed)
     double guess_lo[2];       // MASS: first edge, for the uniform-grid guess
     double guess_inv[2];      // MASS: 1 / bin width
+    int32_t olo;              // identical particles in kernel slots olo, olo + 2 (olo 0 or 1; -1: none)
+    int32_t odir;             // +1: the faster goes to kernel slot olo, -1: to olo + 2
 };
 
 // Launch parameters (kernel argument).  One pass launch covers the samples

@@ -36,7 +36,7 @@ struct EvOut {
     int cls;      // CLS_* (CLS_DEFER: exact tier)
     int bin;      // combined bin, -1 out of range
     int t2;       // float64 recheck of the sign was needed
-    int why;      // deferred at: 1 validity, 2 sign, 3 first axis, 4 second axis
+    int why;      // deferred at: 1 validity, 2 sign, 3 first axis, 4 second axis, 5 order
     double ct;    // C_T^inv estimate
 };
 
@@ -356,7 +356,7 @@ __device__ __forceinline__ int bin_mass(const double x[4][4], const double w[4],
 }
 
 struct Seg {
-    int32_t sigma, nb0, nb1, nbtot, slots0, slots1;
+    int32_t sigma, nb0, nb1, nbtot, slots0, slots1, olo, odir;
     double glo0, ginv0, glo1, ginv1;
     const double *e0, *e1;    // LDS edge data of each axis
 };
@@ -371,6 +371,41 @@ __device__ __forceinline__ int axis_bin(const double (&x)[4][4], const double (&
     if constexpr (KIND == AX_ABSPHI) return bin_absphi_bv(m01, m23, M1, M2s, P, W, ed, nb, sure);
     else if constexpr (KIND == AX_MASS) return bin_mass(x, w, sl, ed, nb, glo, ginv, sure);
     else return bin_abscos<SLOT0>(x, w, W, P, M2, sl, ed, nb, sure);
+}
+
+// Canonical order of two identical particles in kernel slots LO and LO + 2:
+// the one with the larger energy in the M rest frame, i.e. the larger P.p
+// (= M E*), belongs in the channel's "fast" slot (dir = +1: slot LO).  With
+// d = p_LO - p_HI and s = P.d (Minkowski), every rounding is bounded on
+// magnitudes: P_c sums four components (2u of sum_s |x_sc|), d_c one
+// difference (u |d_c|), the four-term product 4u; in all
+// |s_computed - s| <= 8u sum_c (sum_s |x_sc|)(|x_LO,c| + |x_HI,c|)
+//                   <= 8u W (w_LO + w_HI),
+// taken as 8.1u with the bound's own roundings.  A decided event has its rows
+// (and row norms) exchanged when the slow one is stored first; an undecided
+// one -- including an exact tie, which keeps the stored order -- goes to the
+// exact tier.
+template <int LO>
+__device__ __forceinline__ bool order_pair(double (&x)[4][4], double (&w)[4], const double (&P)[4], double W, int dir)
+{
+    constexpr int HI = LO + 2;
+    double d[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) d[c] = x[LO][c] - x[HI][c];
+    const double s = fma(-P[3], d[3], fma(-P[2], d[2], fma(-P[1], d[1], P[0] * d[0])));
+    const double bound = fma((8.1 * U64) * W, w[LO] + w[HI], TINY);
+    if (!(dabs(s) > bound)) return false;
+    const bool sw = (dir > 0) ? (s < 0.0) : (s > 0.0);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const double a = x[LO][c], b = x[HI][c];
+        x[LO][c] = sw ? b : a;
+        x[HI][c] = sw ? a : b;
+    }
+    const double a = w[LO], b = w[HI];
+    w[LO] = sw ? b : a;
+    w[HI] = sw ? a : b;
+    return true;
 }
 
 // Whole event, with the binning scheme (K0, K1; AX_NONE = absent) fixed at
@@ -406,6 +441,12 @@ __device__ __forceinline__ EvOut eval_event(const Tin (&q)[4][4], int tag, const
     const double Emin = fmin(fmin(x[0][0], x[1][0]), fmin(x[2][0], x[3][0]));
     if (!(Emin >= 0.0 && P[0] > 0.0 && M2 > fma((11.0 * U64) * W, W, TINY))) return o;
 
+    if (g.olo >= 0) {   // uniform: identical particles to be ordered
+        o.why = 5;
+        const bool ok = g.olo == 0 ? order_pair<0>(x, w, P, W, g.odir) : order_pair<1>(x, w, P, W, g.odir);
+        if (!ok) return o;
+    }
+
     // Sign of the triple product.  The plane-angle bins need the float64
     // minors (the bivectors p0^p1, p2^p3) anyway, and the determinant from them
     // costs a dozen operations, less than the float32 contraction: so the
@@ -422,7 +463,7 @@ __device__ __forceinline__ EvOut eval_event(const Tin (&q)[4][4], int tag, const
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) qf[s][c] = (float)q[s][c];
+            for (int c = 0; c < 4; ++c) qf[s][c] = (float)x[s][c];   // x holds q exactly (rows possibly ordered)
         sure = det_f32(qf, det32);
         det = (double)det32;
         if (!sure) {
@@ -783,6 +824,8 @@ __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
         g.glo1 = S->guess_lo[1];
         g.ginv0 = S->guess_inv[0];
         g.ginv1 = S->guess_inv[1];
+        g.olo = S->olo;
+        g.odir = S->odir;
         const int nd0 = K0 != AX_NONE ? edge_doubles(K0, g.nb0) : 0;
         const int nd1 = K1 != AX_NONE ? edge_doubles(K1, g.nb1) : 0;
         const int eoff0 = S->eoff[0], eoff1 = S->eoff[1];

@@ -35,7 +35,7 @@ class _Events(ctypes.Structure):
 
 
 class _Channel(ctypes.Structure):
-    _fields_ = [("triple", ctypes.c_int32 * 3), ("planes", ctypes.c_int32 * 4)]
+    _fields_ = [("triple", ctypes.c_int32 * 3), ("planes", ctypes.c_int32 * 4), ("identical", ctypes.c_int32 * 2)]
 
 
 class _Axis(ctypes.Structure):
@@ -166,12 +166,16 @@ class DeviceSample:
         return e
 
 
-def channel(triple, planes=(0, 1, 2, 3)) -> _Channel:
+def channel(triple, planes=(0, 1, 2, 3), identical=None) -> _Channel:
+    """tp_channel; ``identical`` = (fast slot, slow slot) of two identical
+    particles that the pass orders by rest-frame energy, or None."""
     c = _Channel()
     for k in range(3):
         c.triple[k] = int(triple[k])
     for k in range(4):
         c.planes[k] = int(planes[k])
+    f, s = (-1, -1) if identical is None else identical
+    c.identical[0], c.identical[1] = int(f), int(s)
     return c
 
 

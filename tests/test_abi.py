@@ -117,6 +117,13 @@ def test_validation_errors_reach_no_device(tp):
     assert rc_bin(_events(tp), tp.channel((0, 0, 2)), good) == -1
     assert rc_bin(_events(tp), tp.channel((0, 1, 4)), good) == -1
     assert rc_bin(_events(tp), tp.channel((0, 1, 2), (0, 1, 1, 3)), good) == -1
+    # identical particles: two distinct slots of 0..3; with a plane angle binned
+    # they must sit at positions (0, 2) or (1, 3) of planes
+    assert rc_bin(_events(tp), tp.channel((0, 1, 2), identical=(1, 1)), good) == -1
+    assert rc_bin(_events(tp), tp.channel((0, 1, 2), identical=(1, 4)), good) == -1
+    assert rc_bin(_events(tp), tp.channel((0, 1, 2), identical=(1, -1)), good) == -1
+    assert rc_bin(_events(tp), tp.channel((0, 1, 2), identical=(0, 1)), good) == -2
+    assert rc_bin(_events(tp), tp.channel((0, 1, 2), (0, 1, 3, 2), identical=(1, 3)), good) == -2
     e = _events(tp)
     e.p[5] = None
     assert rc_bin(e, ch, good) == -1

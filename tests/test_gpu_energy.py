@@ -19,7 +19,7 @@ from paper_1612_04705_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-# D0 -> K+ K- pi+ pi- coordinates (Sect. 4): m12, m14, m23, m34, m134
+# D0 -> K+ K- pi+ pi- coordinates (Sect. 4.2, Table 1): m12, m14, m23, m34, m134
 MASKS = [0b0011, 0b1001, 0b0110, 0b1100, 0b1101]
 
 
