@@ -281,9 +281,17 @@ int tp_version(void);
 
 /* Invariant masses (times ``scale``, e.g. 1e-3 for MeV -> GeV) of ``ncoord`` (1..8)
  * slot bit masks (1..15) per event: coords [ncoord][ld] float32, device, written.
- * ev as for tp_compute (the tag is not read).  Async on ``stream``. */
-int tp_coords(const tp_events *ev, const int32_t *masks, int32_t ncoord, double scale, float *coords, int64_t ld,
-              void *stream);
+ * ev as for tp_compute (the tag is not read).  Async on ``stream``.
+ * relabel: TP_RELABEL_NONE, or TP_RELABEL_D4PI for D0 -> pi+ pi- pi+ pi- with
+ * the slots in charge order (+ - + -): before the masses are formed, the
+ * pi+ pi- pair of largest invariant mass becomes pi3 pi4 (slots 2, 3), which
+ * fixes the labels of all four pions (Sect. 4.2; Table 1 then selects masks
+ * m12, m14, m23, m123, m124, i.e. 0x3, 0x9, 0x6, 0x7, 0xB).  The mass
+ * comparisons are certified (float64 with an error bound, exact integers
+ * otherwise); equal masses go to the first pair of (2,3), (0,1), (0,3), (2,1). */
+enum { TP_RELABEL_NONE = 0, TP_RELABEL_D4PI = 1 };
+int tp_coords(const tp_events *ev, const int32_t *masks, int32_t ncoord, double scale, int32_t relabel,
+              float *coords, int64_t ld, void *stream);
 
 /* Pair sums above.  coords [dims][ld] float32 (device, dims 1..8, ld >= n);
  * cols [n][ncols] uint8 0/1 (device, row-major, 16-byte aligned, ncols 32, 64

@@ -6,7 +6,9 @@ use this module.  It shares no code with the HIP path.
 Follows the paper's Sect. 2.2 (energy test) and Sect. 3 (background) directly:
 
 * coordinates: invariant masses of particle combinations (Sect. 4.2, Table 1),
-  computed from the stored four-vectors in float64;
+  computed from the stored four-vectors in float64; for D0 -> pi+ pi- pi+ pi-
+  the pions are first labelled by the rule of Sect. 4.2 (the pi+ pi- pair of
+  largest invariant mass is pi3 pi4), see ``d4pi_perm``;
 * psi_ij = exp(-d_ij^2 / (2 sigma^2)), d_ij the Euclidean distance between the
   coordinate vectors of events i and j (Sect. 2.2);
 * T of eq. (2): the two within-sample averages over pairs i < j minus the
@@ -20,16 +22,69 @@ All sums are plain float64 over explicit pairs (blocked only to bound memory).
 """
 from __future__ import annotations
 
+from fractions import Fraction
+
 import numpy as np
 
 
-def invariant_masses(comps, masks):
+# the four pi+ pi- pairs of (+ - + -) slots, and the labelling that makes each
+# of them pi3 pi4 (new slot t holds stored slot perm[t]); listed in the order
+# that decides ties: the stored labelling, then both pairs swapped, then the
+# pi+ swapped, then the pi- swapped
+D4PI_PAIRS = ((2, 3), (0, 1), (0, 3), (2, 1))
+D4PI_PERMS = ((0, 1, 2, 3), (2, 3, 0, 1), (2, 1, 0, 3), (0, 3, 2, 1))
+
+
+def _pair_m2(x, a, b):
+    S = x[a] + x[b]
+    return S[0] ** 2 - S[1] ** 2 - S[2] ** 2 - S[3] ** 2
+
+
+def _pair_m2_exact(x, i, a, b):
+    S = [Fraction(float(x[a][c][i])) + Fraction(float(x[b][c][i])) for c in range(4)]
+    return S[0] ** 2 - S[1] ** 2 - S[2] ** 2 - S[3] ** 2
+
+
+def d4pi_perm(comps):
+    """Per event, the index (into D4PI_PERMS) of the labelling of Sect. 4.2 for
+    D0 -> pi+ pi- pi+ pi- stored in charge order: the pi+ pi- pair with the
+    largest invariant mass becomes pi3 pi4.  Masses squared in float64; a
+    comparison within 1e-9 of the pair's magnitude scale is redone in exact
+    rational arithmetic; equal masses keep the earlier pair of D4PI_PAIRS."""
+    x = np.asarray(comps, dtype=np.float64)
+    n = x.shape[2]
+    m2 = np.array([_pair_m2(x, a, b) for a, b in D4PI_PAIRS])
+    scale = np.array([(np.abs(x[a]) + np.abs(x[b])).sum(axis=0) ** 2 for a, b in D4PI_PAIRS])
+    best = np.zeros(n, dtype=np.int64)
+    idx = np.arange(n)
+    for k in range(1, 4):
+        d = m2[k] - m2[best, idx]
+        near = np.abs(d) <= 1e-9 * (scale[k] + scale[best, idx])
+        best = np.where(~near & (d > 0), k, best)
+        for i in np.nonzero(near)[0]:
+            a, b = D4PI_PAIRS[k]
+            c, e = D4PI_PAIRS[best[i]]
+            if _pair_m2_exact(x, i, a, b) > _pair_m2_exact(x, i, c, e):
+                best[i] = k
+    return best
+
+
+def invariant_masses(comps, masks, relabel=None):
     """Invariant mass of the slots in each bit mask, per event.
 
     comps: [4 slots][4 comps (E, px, py, pz)][n]; masks: iterable of slot bit
     masks.  Returns float64 [len(masks)][n]; m = sqrt(max(m^2, 0)).
+    relabel="d4pi": slots hold pi+ pi- pi+ pi- and are labelled by ``d4pi_perm``
+    before the masses are formed.
     """
     x = np.asarray(comps, dtype=np.float64)
+    if relabel == "d4pi":
+        best = d4pi_perm(x)
+        perm = np.array(D4PI_PERMS)[best]          # [n][4]
+        idx = np.arange(x.shape[2])
+        x = np.stack([x[perm[:, t], :, idx].T for t in range(4)])
+    elif relabel is not None:
+        raise ValueError("relabel must be None or 'd4pi'")
     out = []
     for m in masks:
         S = np.zeros((4, x.shape[2]))

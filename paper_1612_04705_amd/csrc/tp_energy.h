@@ -30,6 +30,7 @@ struct CParams {
     double scale;             // unit factor applied to the masses
     float *out;               // [ncoord][ldo], device
     int64_t ldo;
+    int32_t relabel;          // 0: stored slots; 1: pi+ pi- pi+ pi- rule (largest-mass pair to slots 2, 3)
 };
 
 hipError_t launch_pairsums(const EParams &p, hipStream_t st);

@@ -31,6 +31,8 @@
 #include <stdint.h>
 
 #include "tp_energy.h"
+#define TP_HD __host__ __device__
+#include "tp_exact.h"
 
 namespace tpe {
 namespace {
@@ -337,18 +339,72 @@ void launch_nt(const EParams &p, hipStream_t st)
     else launch_ntr<NT, 3>(p, st);
 }
 
+// Certified order of two pair masses m^2(a, b) against m^2(c, d): +1 if
+// larger, -1 if smaller, 0 if equal.  float64 with the magnitude bound
+// |m^2_computed - m^2| <= 8u (sum_q |x_aq| + |x_bq|)^2 (one rounding for each
+// component sum, four for the squares and their sum), exact integers when the
+// two intervals overlap.
+template <typename Tin>
+__device__ int pair_cmp(const double (&x)[4][4], int a, int b, int c, int d)
+{
+    double m2[2], mag[2];
+    const int sl[2][2] = { { a, b }, { c, d } };
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        double S[4], A = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            S[q] = x[sl[k][0]][q] + x[sl[k][1]][q];
+            A += __builtin_fabs(x[sl[k][0]][q]) + __builtin_fabs(x[sl[k][1]][q]);
+        }
+        m2[k] = fma(-S[3], S[3], fma(-S[2], S[2], fma(-S[1], S[1], S[0] * S[0])));
+        mag[k] = fma(8.0 * 0x1p-53 * A, A, 0x1p-1000);
+    }
+    const double diff = m2[0] - m2[1];
+    const double err = (mag[0] + mag[1]) * (1.0 + 0x1p-50);
+    if (diff > err) return 1;
+    if (diff < -err) return -1;
+    int64_t mant[4][4];
+    int ex[4][4];
+    for (int s = 0; s < 4; ++s)
+        for (int q = 0; q < 4; ++q) {
+            if constexpr (sizeof(Tin) == 4) tpx::decode_f32((float)x[s][q], mant[s][q], ex[s][q]);
+            else tpx::decode_f64(x[s][q], mant[s][q], ex[s][q]);
+        }
+    const int r = tpx::pair_mass2_cmp(mant, ex, sizeof(Tin) == 4 ? 136 : 107, a, b, c, d);
+    return r == 2 ? 0 : r;
+}
+
 // Invariant mass of the slots in a mask, per event (Sect. 4.2 coordinates).
+// With relabel 1 (D0 -> pi+ pi- pi+ pi-, slots in charge order + - + -) the
+// event is first relabelled as Sect. 4.2 prescribes: of the four pi+ pi- pairs
+// the one of largest invariant mass becomes pi3 pi4 (slots 2, 3), which fixes
+// the order of all four pions.  Ties go to the first pair in the order
+// (2,3), (0,1), (0,3), (2,1) (the stored labelling, then the swap of both
+// pairs, of the pi+, of the pi-).
 template <typename Tin>
 __global__ void tp_coords_kernel(CParams c)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= c.n) return;
     const Tin *const *P = reinterpret_cast<const Tin *const *>(c.p);
+    double x[4][4];
+    for (int s = 0; s < 4; ++s)
+        for (int q = 0; q < 4; ++q) x[s][q] = (double)P[s * 4 + q][e];
+    int perm[4] = { 0, 1, 2, 3 };   // new slot t holds stored slot perm[t]
+    if (c.relabel == 1) {
+        const int pa[4][2] = { { 2, 3 }, { 0, 1 }, { 0, 3 }, { 2, 1 } };
+        const int pm[4][4] = { { 0, 1, 2, 3 }, { 2, 3, 0, 1 }, { 2, 1, 0, 3 }, { 0, 3, 2, 1 } };
+        int best = 0;
+        for (int k = 1; k < 4; ++k)
+            if (pair_cmp<Tin>(x, pa[k][0], pa[k][1], pa[best][0], pa[best][1]) > 0) best = k;
+        for (int t = 0; t < 4; ++t) perm[t] = pm[best][t];
+    }
     for (int k = 0; k < c.ncoord; ++k) {
         double S[4] = { 0.0, 0.0, 0.0, 0.0 };
         for (int s = 0; s < 4; ++s)
             if (c.masks[k] & (1 << s))
-                for (int q = 0; q < 4; ++q) S[q] += (double)P[s * 4 + q][e];
+                for (int q = 0; q < 4; ++q) S[q] += x[perm[s]][q];
         const double m2 = S[0] * S[0] - S[1] * S[1] - S[2] * S[2] - S[3] * S[3];
         c.out[(int64_t)k * c.ldo + e] = (float)(m2 > 0.0 ? sqrt(m2) * c.scale : 0.0);
     }

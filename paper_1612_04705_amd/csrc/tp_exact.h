@@ -351,6 +351,22 @@ TP_HD inline int order_sign(const int64_t mant[4][4], const int ex[4][4], int sp
     return ev.ok ? big_sign(d) : 2;
 }
 
+// Exact sign of m^2(a, b) - m^2(c, d), m^2(x, y) = (p_x + p_y)^2, or 2 if the
+// event exceeds the arithmetic's capacity.
+TP_HD inline int pair_mass2_cmp(const int64_t mant[4][4], const int ex[4][4], int span, int a, int b, int c, int d)
+{
+    Event ev;
+    if (!event_build(ev, mant, ex, span)) return 2;
+    Big<L1> S1[4], S2[4];
+    for (int k = 0; k < 4; ++k) {
+        ev.ok = ev.ok && big_addsub(S1[k], ev.q[a][k], ev.q[b][k], 1);
+        ev.ok = ev.ok && big_addsub(S2[k], ev.q[c][k], ev.q[d][k], 1);
+    }
+    Big<L2> m1, m2, diff;
+    ev.ok = ev.ok && mdot(m1, S1, S1) && mdot(m2, S2, S2) && big_addsub(diff, m1, m2, -1);
+    return ev.ok ? big_sign(diff) : 2;
+}
+
 // E_P > 0 and M^2 > 0
 TP_HD inline bool event_timelike(const Event &ev)
 {

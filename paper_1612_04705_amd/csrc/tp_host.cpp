@@ -1228,9 +1228,10 @@ const char *tp_strerror(int status)
 int tp_version(void) { return TPASYM_VERSION; }
 
 // ------------------------------------------------------------ energy test
-int tp_coords(const tp_events *ev, const int32_t *masks, int32_t ncoord, double scale, float *coords, int64_t ld,
-              void *stream)
+int tp_coords(const tp_events *ev, const int32_t *masks, int32_t ncoord, double scale, int32_t relabel,
+              float *coords, int64_t ld, void *stream)
 {
+    if (relabel != TP_RELABEL_NONE && relabel != TP_RELABEL_D4PI) return fail(TP_EINVAL, "unknown relabel");
     if (!ev || !masks || !coords) return fail(TP_EINVAL, "null pointer");
     if (ev->n < 0 || ev->n >= (int64_t(1) << 40)) return fail(TP_ERANGE, "n out of range");
     if (ev->dtype != TP_F32 && ev->dtype != TP_F64) return fail(TP_EINVAL, "dtype must be TP_F32 or TP_F64");
@@ -1254,6 +1255,7 @@ int tp_coords(const tp_events *ev, const int32_t *masks, int32_t ncoord, double 
     c.scale = scale;
     c.out = coords;
     c.ldo = ld;
+    c.relabel = relabel;
     TP_HIP(tpe::launch_coords(c, ev->dtype, static_cast<hipStream_t>(stream)));
     return TP_OK;
 }

@@ -73,6 +73,9 @@ CHANNELS = {
     "Lb_pKKK": Channel("Lb_pKKK", M_LB, (M_P, M_K, M_K, M_K), (0, 1, 2), identical=(1, 3)),
     # D0 -> K+ K- pi+ pi-, C_T = p_K+ . (p_pi+ x p_pi-)
     "D0_KKpipi": Channel("D0_KKpipi", M_D0, (M_K, M_K, M_PI, M_PI), (0, 2, 3)),
+    # D0 -> pi+ pi- pi+ pi- (charge order), for the energy-test coordinates: the
+    # labelling of the identical pions is left to the coordinates' own rule
+    "D0_pipipipi": Channel("D0_pipipipi", M_D0, (M_PI, M_PI, M_PI, M_PI), (0, 1, 2)),
 }
 
 # axis kinds (same numbering as the C-ABI)

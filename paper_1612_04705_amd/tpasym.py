@@ -97,8 +97,8 @@ def load():
         "tp_release": [],
         "tp_strerror": [ctypes.c_int],
         "tp_version": [],
-        "tp_coords": [P(_Events), P(ctypes.c_int32), ctypes.c_int32, ctypes.c_double, ctypes.c_void_p,
-                      ctypes.c_int64, ctypes.c_void_p],
+        "tp_coords": [P(_Events), P(ctypes.c_int32), ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                      ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p],
         "tp_pairsums": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
                         ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p],
         "tp_energy_eq2": [P(ctypes.c_double), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -308,14 +308,18 @@ def version():
 
 
 # ------------------------------------------------------------------ energy test
-def coords(ds: DeviceSample, masks, scale=1e-3, out=None, stream=None):
-    """Invariant masses (x scale) of the slot masks, float32 [len(masks)][n] on the device."""
+TP_RELABEL_NONE, TP_RELABEL_D4PI = 0, 1
+
+
+def coords(ds: DeviceSample, masks, scale=1e-3, out=None, stream=None, relabel=TP_RELABEL_NONE):
+    """Invariant masses (x scale) of the slot masks, float32 [len(masks)][n] on
+    the device; relabel=TP_RELABEL_D4PI applies the pi+ pi- pi+ pi- labelling rule."""
     m = (ctypes.c_int32 * len(masks))(*masks)
     if out is None:
         out = torch.empty((len(masks), ds.n), dtype=torch.float32, device=ds.tag.device)
     e = ds.events()
-    _check(load().tp_coords(ctypes.byref(e), m, len(masks), float(scale), ctypes.c_void_p(out.data_ptr()),
-                            out.stride(0), _stream(stream)))
+    _check(load().tp_coords(ctypes.byref(e), m, len(masks), float(scale), int(relabel),
+                            ctypes.c_void_p(out.data_ptr()), out.stride(0), _stream(stream)))
     return out
 
 

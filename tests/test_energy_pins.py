@@ -101,3 +101,58 @@ def test_invariant_mass_hand_event():
     comps[1, :, 0] = [1.0, 0.0, 0.0, -1.0]
     m = energy.invariant_masses(comps, [0b0011, 0b0001])
     assert m[0, 0] == 2.0 and m[1, 0] == 0.0
+
+
+# ---- D0 -> pi+ pi- pi+ pi- labelling (Sect. 4.2): the pi+ pi- pair of largest
+# invariant mass becomes pi3 pi4
+D4PI_MASKS = [0b0011, 0b1001, 0b0110, 0b0111, 0b1011]     # m12, m14, m23, m123, m124 (Table 1)
+
+
+def test_d4pi_hand_event():
+    # at rest: pi+_0 = (5, 1, 0, 0), pi-_1 = (5, -1, 0, 0), pi+_2 = (4, 0, 1, 0), pi-_3 = (4, 0, -1, 0)
+    # pair masses^2: (0,1) 100, (2,3) 64, (0,3) = (9, 1, -1, 0) -> 79, (2,1) -> 79;
+    # the largest, (0,1), becomes pi3 pi4: new order (2, 3, 0, 1), so
+    # m12^2 = 64, m14^2 = m23^2 = 79, m123^2 = m124^2 = 13^2 - 1 = 168
+    comps = np.array([[5, 1, 0, 0], [5, -1, 0, 0], [4, 0, 1, 0], [4, 0, -1, 0]], dtype=np.float64).reshape(4, 4, 1)
+    assert list(energy.d4pi_perm(comps)) == [1]
+    m2 = energy.invariant_masses(comps, D4PI_MASKS, relabel="d4pi")[:, 0] ** 2
+    assert np.allclose(m2, [64, 79, 79, 168, 168], rtol=1e-15)
+
+
+def test_d4pi_labels_do_not_depend_on_stored_order():
+    ch = synth.CHANNELS["D0_pipipipi"]
+    comps, _ = synth.generate(ch, 4000, 12).numpy()
+    want = energy.invariant_masses(comps, D4PI_MASKS, relabel="d4pi")
+    for perm in ((2, 1, 0, 3), (0, 3, 2, 1), (2, 3, 0, 1)):      # swap pi+, swap pi-, swap both
+        got = energy.invariant_masses(comps[list(perm)], D4PI_MASKS, relabel="d4pi")
+        assert np.array_equal(got, want)
+    # without the rule the coordinates do depend on it
+    assert not np.array_equal(energy.invariant_masses(comps[[2, 1, 0, 3]], D4PI_MASKS),
+                              energy.invariant_masses(comps, D4PI_MASKS))
+
+
+def test_d4pi_largest_pair_is_pi3_pi4():
+    ch = synth.CHANNELS["D0_pipipipi"]
+    comps, _ = synth.generate(ch, 3000, 13).numpy()
+    m = energy.invariant_masses(comps, [0b1100, 0b0011, 0b1001, 0b0110], relabel="d4pi")
+    # every pi+ pi- pair of the labelled event: (3,4), (1,2), (1,4), (3,2) in 1-based slots
+    assert np.all(m[0] >= m[1:].max(axis=0))
+
+
+def test_d4pi_exact_tie_keeps_first_pair():
+    # (0,3) and (2,1) tie for the largest mass: the earlier of the two, (0,3), wins
+    comps = np.array([[5, 1, 0, 0], [5, 0, 1, 0], [5, -1, 0, 0], [5, 0, -1, 0]], dtype=np.float64).reshape(4, 4, 1)
+    # (0,1): (10, 1, 1, 0) -> 98; (2,3): (10, -1, -1, 0) -> 98; (0,3): (10, 1, -1, 0) -> 98; (2,1) -> 98
+    # all four tie: the stored labelling stays
+    assert list(energy.d4pi_perm(comps)) == [0]
+    comps2 = np.array([[6, 1, 0, 0], [5, 0, 1, 0], [6, -1, 0, 0], [5, 0, -1, 0]], dtype=np.float64).reshape(4, 4, 1)
+    # (0,1) = (11, 1, 1, 0) -> 119 = (2,3); (0,3) = (11, 1, -1, 0) -> 119 = (2,1): all tie again
+    assert list(energy.d4pi_perm(comps2)) == [0]
+    comps3 = np.array([[6, 1, 0, 0], [5, 0, 1, 0], [6, -1, 0, 0], [5, 0, 1, 0]], dtype=np.float64).reshape(4, 4, 1)
+    # (2,3) = (11, -1, 1, 0) -> 119, (0,1) = (11, 1, 1, 0) -> 119, (0,3) = (11, 1, 1, 0) -> 119,
+    # (2,1) = (11, -1, 1, 0) -> 119: ties keep the stored labelling
+    assert list(energy.d4pi_perm(comps3)) == [0]
+    comps4 = np.array([[6, 1, 0, 0], [5, 1, 0, 0], [6, -1, 0, 0], [5, -1, 0, 0]], dtype=np.float64).reshape(4, 4, 1)
+    # (2,3) = (11, -2, 0, 0) -> 117, (0,1) = (11, 2, 0, 0) -> 117, (0,3) = (11, 0, 0, 0) -> 121,
+    # (2,1) = (11, 0, 0, 0) -> 121: (0,3) and (2,1) tie above the others; (0,3) comes first
+    assert list(energy.d4pi_perm(comps4)) == [2]

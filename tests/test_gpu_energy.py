@@ -178,3 +178,43 @@ def test_full_size_sampled_sums(tp):
     want_diag = energy.pair_sum(Yo[:, pick], Yo[:, pick], 0.3, True)
     assert abs(S[1, 1] - want_all) <= 1e-5 * want_all
     assert abs(S[1, 0] - want_diag) <= 1e-5 * want_all
+
+
+D4PI_MASKS = [0b0011, 0b1001, 0b0110, 0b0111, 0b1011]     # m12, m14, m23, m123, m124 (Sect. 4.2, Table 1)
+
+
+def _d4pi_check(tp, comps, label):
+    s = synth.Sample(synth.CHANNELS["D0_pipipipi"],
+                     [[torch.from_numpy(np.ascontiguousarray(comps[a][b])) for b in range(4)] for a in range(4)],
+                     torch.zeros(comps.shape[2], dtype=torch.int8))
+    ds = tp.DeviceSample.from_sample(s)
+    Yg = tp.coords(ds, D4PI_MASKS, 1e-3, relabel=tp.TP_RELABEL_D4PI).cpu().numpy().astype(np.float64)
+    Yo = energy.invariant_masses(comps, D4PI_MASKS, relabel="d4pi") * 1e-3
+    W = np.abs(comps.astype(np.float64)).sum(axis=(0, 1)) * 1e-3
+    tol = 2.0 * W * W * 2.0 ** -53 * 64 / np.maximum(Yo, 1e-3) + 2.0 ** -23 * Yo
+    bad = np.abs(Yg - Yo) > tol
+    print(f"[coords] {label}: {int(bad.any(axis=0).sum())} of {comps.shape[2]} events off", flush=True)
+    assert not bad.any()
+
+
+def test_coords_d4pi_relabel_matches_oracle(tp):
+    ch = synth.CHANNELS["D0_pipipipi"]
+    comps, _ = synth.generate(ch, 5003, 82).numpy()
+    # store the identical pions in a random order per event
+    k = np.random.default_rng(4).integers(0, 4, size=comps.shape[2])
+    perms = np.array(energy.D4PI_PERMS)[k]
+    idx = np.arange(comps.shape[2])
+    shuffled = np.stack([comps[perms[:, t], :, idx].T for t in range(4)])
+    _d4pi_check(tp, shuffled, "shuffled pions")
+
+
+def test_coords_d4pi_exact_ties(tp):
+    # small-integer events with tied pair masses (exact path, stored-order ties)
+    rng = np.random.default_rng(6)
+    rows = []
+    for _ in range(257):
+        a, b = (int(v) for v in rng.integers(1, 6, size=2))
+        E1, E2 = (int(v) for v in rng.integers(10, 14, size=2))
+        rows.append([[E1, a, 0, 0], [E2, 0, b, 0], [E1, -a, 0, 0], [E2, 0, -b, 0]])
+    comps = np.array(rows, dtype=np.float32).transpose(1, 2, 0).copy()
+    _d4pi_check(tp, comps, "ties")
