@@ -198,6 +198,8 @@ def main():
                     help="events of the energy-test leg (0 skips it)")
     ap.add_argument("--energy-perms", type=int, default=126,
                     help="permutations evaluated in one pass (columns = perms + 2, at most 128)")
+    ap.add_argument("--no-ordered", action="store_true",
+                    help="skip the leg that repeats the pass with the identical particles ordered on the fly")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -293,6 +295,33 @@ def main():
         f64_leg = {"value": nevents / (f64_ms / 1e3), "unit": "events/s", "ms_per_step": f64_ms,
                    "counts_equal_fast_path": bool(agree)}
 
+    # the same pass with the identical particles (two pi- or two K-) ordered on
+    # the fly by rest-frame energy: the stored order is then irrelevant
+    ord_leg = None
+    if not args.no_ordered:
+        ord_items = [(ds, tpasym.channel(spec.channel.triple, spec.channel.planes, spec.channel.identical), bn,
+                      *tpasym.new_counts(bn, dev)) for (ds, _, bn, _, _), (spec, _) in zip(items, samples)]
+        nord = sum(1 for spec, _ in samples if spec.channel.identical is not None)
+        ob = tpasym.Batch(ord_items)
+        ob.run(prec, tuning, graph)
+        torch.cuda.synchronize()
+        osteps = max(5, args.steps // 4)
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(osteps):
+            ob.run(prec, tuning, graph)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        o_ms = t0.elapsed_time(t1) / osteps
+        # the generator stored them in order (float64, before the boost): the
+        # counts may differ only by events whose two energies tie to float32 rounding
+        moved = sum(int(np.abs(a[3].cpu().numpy().view(np.uint64).astype(np.int64) // reps
+                               - b[3].cpu().numpy().view(np.uint64).astype(np.int64) // (osteps + 1)).sum())
+                    for a, b in zip(items, ord_items))
+        ord_leg = {"value": nevents / (o_ms / 1e3), "unit": "events/s", "ms_per_step": o_ms,
+                   "samples_with_identical_particles": nord, "count_changes_vs_stored_order": moved}
+        log(f"ordered pass: {o_ms:.4f} ms/step ({nord} samples ordered on the fly), count changes {moved}")
+
     wl = args.workload
     if args.scale != 1.0:
         wl += f"_scale{args.scale:g}"
@@ -320,6 +349,7 @@ def main():
                      "traffic": traffic,
                      "bytes_per_event": bpe, "kernel_ms": kern_ms, "kernel_launches": launches},
         "fp64_single_sample": f64_leg,
+        "ordered_identical": ord_leg,
         "tiers": {"tier2_per_step": tier2, "tier3_per_step": tier3, "unresolved_per_step": unres},
         "paper_context": "energy test (different algorithm): 1e6 events, one permutation ~30 min on "
                          "NVIDIA M2070 / K40c (Sect. 6); no timing is given for the triple-product pass",

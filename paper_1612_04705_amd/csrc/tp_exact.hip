@@ -16,6 +16,26 @@ namespace {
 
 __device__ __forceinline__ double dabs(double x) { return __builtin_fabs(x); }
 
+// Rest-frame energy order of kernel slots lo, lo + 2 in float64 (the pass's
+// test: s = P.(p_lo - p_hi) against 8.1u W (w_lo + w_hi)): +1 if p_lo is
+// faster, -1 if slower, 0 if the bound does not settle it.
+__device__ __forceinline__ int order_f64(const double (&x)[4][4], int lo)
+{
+    const int hi = lo + 2;
+    double P[4], w[4], W = 0.0;
+    for (int c = 0; c < 4; ++c) P[c] = (x[0][c] + x[1][c]) + (x[2][c] + x[3][c]);
+    for (int k = 0; k < 4; ++k) {
+        w[k] = (dabs(x[k][0]) + dabs(x[k][1])) + (dabs(x[k][2]) + dabs(x[k][3]));
+        W += w[k];
+    }
+    double d[4];
+    for (int c = 0; c < 4; ++c) d[c] = x[lo][c] - x[hi][c];
+    const double sv = fma(-P[3], d[3], fma(-P[2], d[2], fma(-P[1], d[1], P[0] * d[0])));
+    const double bound = fma((8.2 * 0x1p-53) * W, w[lo] + w[hi], 0x1p-1000);
+    if (!(dabs(sv) > bound)) return 0;
+    return sv > 0.0 ? 1 : -1;
+}
+
 // ------------------------------------------------------------------ exact tier
 template <typename Tin, int MODE>
 __global__ __launch_bounds__(64) void tp_exact_kernel(const KParams kp)
@@ -43,7 +63,15 @@ __global__ __launch_bounds__(64) void tp_exact_kernel(const KParams kp)
         // identical particles: exact rest-frame energy order first (an exact
         // tie keeps the stored order), then every decision on the ordered rows
         bool order_unres = false;
-        if (finite && S.olo >= 0) {
+        int osg = (finite && S.olo >= 0) ? order_f64(xv, S.olo) : 0;
+        if (osg != 0 && osg * S.odir < 0) {
+            for (int c = 0; c < 4; ++c) {
+                const double t = xv[S.olo][c];
+                xv[S.olo][c] = xv[S.olo + 2][c];
+                xv[S.olo + 2][c] = t;
+            }
+        }
+        if (finite && S.olo >= 0 && osg == 0) {
             int64_t om[4][4];
             int oe[4][4];
             for (int k = 0; k < 4; ++k)
