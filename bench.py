@@ -187,6 +187,77 @@ def energy_leg(n, nperm, dev, per_pass=126):
             "paper_context": "one permutation at 1e6 events took ~30 min on NVIDIA M2070 / K40c (Sect. 6)"}
 
 
+def energy_bkg_leg(n, nperm, dev, bkg_frac=0.2, per_launch=41):
+    """Background-subtracted energy test (eq. (3)) at the same scale: a main
+    sample and a background (side-band) sample of the same coordinates, the
+    P-odd flavour split in each, and ``nperm`` permutations that shuffle the
+    flavour within the main and within the background sample.  One launch of
+    128 columns carries the two sample indicators (also the row weights), the
+    observed flavour triple and ``per_launch`` permuted triples."""
+    import numpy as np
+    import torch
+    from paper_1612_04705_amd import synth, tpasym
+    ch = synth.CHANNELS["D0_KKpipi"]
+    nb = int(n * bkg_frac)
+    nm = n - nb
+    masks = [0b0011, 0b1001, 0b0110, 0b1100, 0b1101]
+    Ys, labs = [], []
+    for size, seed, inj in ((nm, 78, synth.INJ_SGN), (nb, 79, None)):
+        spec = synth.SampleSpec(ch, size, seed, [], inj=inj)
+        smp = synth.make_sample(spec, device=dev)
+        ds = tpasym.DeviceSample([smp.comps[a][b] for a in range(4) for b in range(4)], smp.tag)
+        Ys.append(tpasym.coords(ds, masks, 1e-3))
+        cls, _, _ = tpasym.compute(ds, tpasym.channel(ch.triple, ch.planes), tpasym.TP_PREC_F32_RECHECK)
+        labs.append(((cls == 0) | (cls == 3)).to(torch.uint8))
+    Y = torch.cat(Ys, dim=1).contiguous()
+    fm, fb = labs
+    g = torch.Generator(device=dev)
+    g.manual_seed(4321)
+    ks = [min(per_launch, nperm - p0) for p0 in range(0, nperm, per_launch)]
+    colsets = []
+    for k in ks:
+        cols = torch.zeros((n, 128), dtype=torch.uint8, device=dev)
+        cols[:nm, 0] = 1
+        cols[nm:, 1] = 1
+        for q in range(k + 1):            # triple 0: the observed flavours
+            a = fm if q == 0 else fm[torch.randperm(nm, generator=g, device=dev)]
+            bt = fb if q == 0 else fb[torch.randperm(nb, generator=g, device=dev)]
+            cols[:nm, 2 + 3 * q] = a
+            cols[nm:, 3 + 3 * q] = bt
+            cols[:nm, 4 + 3 * q] = a
+            cols[nm:, 4 + 3 * q] = bt
+        colsets.append(cols.contiguous())
+    sigma = 0.3
+    tpasym.pairsums(Y, colsets[0], sigma, nrow=2)               # warm-up
+    torch.cuda.synchronize()
+    sums = [torch.zeros((128, 3), dtype=torch.float64, device=dev) for _ in colsets]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for c, sm in zip(colsets, sums):
+        tpasym.pairsums(Y, c, sigma, nrow=2, sums=sm)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    n_x, n_xb = int(fm.sum()), nm - int(fm.sum())
+    b_x, b_xb = int(fb.sum()), nb - int(fb.sum())
+    # expected background in the main sample: the main sample is read as
+    # signal plus a background like the side band, in proportion bkg_frac
+    b, b_bar = bkg_frac * n_x, bkg_frac * n_xb
+    T_obs, T_perm = None, []
+    for sm, k in zip(sums, ks):
+        triples = [(2 + 3 * q, 3 + 3 * q, 4 + 3 * q) for q in range(k + 1)]
+        T = tpasym.energy_eq3(sm.cpu().numpy(), 0, 1, 0, 1, triples, n_x, n_xb, b_x, b_xb, b, b_bar)
+        if T_obs is None:
+            T_obs = float(T[0])
+        T_perm.extend(float(t) for t in T[1:])
+    T_perm = np.array(T_perm)
+    log(f"energy test with background (eq. 3): {nm} + {nb} events, {nperm} permutations in {len(ks)} "
+        f"launches, {sec * 1e3:.1f} ms, {sec * 1e3 / nperm:.2f} ms per permutation, T = {T_obs:.4e}")
+    return {"events_main": nm, "events_background": nb, "permutations": nperm, "launches": len(ks),
+            "seconds": sec, "ms_per_permutation": sec * 1e3 / nperm, "b": b, "b_bar": b_bar,
+            "T_obs": T_obs, "p_value": float(np.count_nonzero(T_perm > T_obs)) / nperm}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,6 +281,8 @@ def main():
                     help="permutations of the energy-test leg, 126 per launch of 128 columns")
     ap.add_argument("--no-ordered", action="store_true",
                     help="skip the leg that repeats the pass with the identical particles ordered on the fly")
+    ap.add_argument("--energy-bkg-perms", type=int, default=164,
+                    help="permutations of the background-subtracted (eq. 3) leg, 41 per launch (0 skips it)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -383,6 +456,8 @@ def main():
         log(f"cpu baseline {cpu['value']:.3e} events/s on {cpu['cores']} threads ({cpu['seconds']:.1f}s)")
     if args.energy_events > 0:
         out["energy_test"] = energy_leg(int(args.energy_events), args.energy_perms, dev)
+        if args.energy_bkg_perms > 0:
+            out["energy_test_background"] = energy_bkg_leg(int(args.energy_events), args.energy_bkg_perms, dev)
     print(json.dumps(out), flush=True)
 
 
