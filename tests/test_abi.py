@@ -153,3 +153,74 @@ def test_validation_errors_reach_no_device(tp):
     assert lib.tp_batch(None, 0, 0, None, 4, None) == -1
     assert lib.tp_asym(None, 1, None) == -1
     assert lib.tp_scp(None, 1, 0, None, None, None, None) == -1
+
+
+def test_energy_entry_points_validate_before_any_launch(tp):
+    lib = tp.load()
+    P = ctypes.c_void_p
+    Y, G, S = P(0x200000), P(0x300000), P(0x400000)
+
+    def ps(coords=Y, dims=5, ld=1000, n=1000, sigma=0.3, cols=G, ncols=32, nrow=1, sums=S):
+        return lib.tp_pairsums(coords, dims, ld, n, sigma, cols, ncols, nrow, sums, None)
+
+    assert ps(coords=None) == -1 and ps(cols=None) == -1 and ps(sums=None) == -1
+    assert ps(dims=0) == -5 and ps(dims=9) == -5
+    assert ps(n=-1) == -5 and ps(ld=999) == -1
+    assert ps(ncols=48) == -1 and ps(ncols=256) == -1
+    assert ps(nrow=4) == -5 and ps(nrow=-1) == -5
+    assert ps(cols=P(0x300001)) == -1                      # columns must be 16-byte aligned
+    for bad in (0.0, -1.0, float("inf"), float("nan")):
+        assert ps(sigma=bad) == -1
+    assert ps(n=1, ld=1) == 0                              # fewer than two events: nothing to do
+    e = _events(tp, n=1000)
+    m = (ctypes.c_int32 * 5)(3, 9, 6, 12, 13)
+
+    def co(ev=e, masks=m, ncoord=5, scale=1e-3, relabel=0, out=Y, ld=1000):
+        return lib.tp_coords(ctypes.byref(ev) if ev is not None else None, masks, ncoord, scale, relabel, out, ld,
+                             None)
+
+    assert co(ev=None) == -1 and co(out=None) == -1
+    assert co(relabel=2) == -1
+    assert co(ncoord=0) == -5 and co(ncoord=9) == -5
+    assert co(masks=(ctypes.c_int32 * 5)(3, 9, 0, 12, 13)) == -1
+    assert co(masks=(ctypes.c_int32 * 5)(3, 9, 16, 12, 13)) == -1
+    assert co(scale=0.0) == -1 and co(ld=999) == -1
+    assert co(ev=_events(tp, n=0)) == 0
+
+
+def test_energy_host_forms_vanish_when_psi_is_one(tp):
+    # psi = 1 for every pair: every ordered-pair sum is a product of counts, and
+    # both eq. (2) and eq. (3) reduce to 0 (the b(b+1) coefficient of eq. (3) is
+    # what makes its background brackets cancel)
+    rng = np.random.default_rng(9)
+    n, C = 1000, 32
+    G = (rng.uniform(size=(n, C)) < 0.4).astype(np.int64)
+    G[:, 0] = 1
+    k = G.sum(axis=0)
+    S = np.zeros((C, 2))
+    S[:, 0] = k * (k - 1)
+    S[:, 1] = (n - 1) * k                                      # sum_i sum_{j != i} 1 * G_jc
+    T = tp.energy_eq2(S, k, n, ones_row=0, ones_col=0)
+    assert np.all(np.abs(T[1:]) < 1e-12)
+    # eq. (3): main rows 0..599, background rows 600..999; flavour columns a, beta, gamma
+    nm = 600
+    main = np.r_[np.ones(nm), np.zeros(n - nm)]
+    bkg = 1 - main
+    cols = [main, bkg]
+    triples = []
+    for t in range(3):
+        fa = (rng.uniform(size=n) < 0.5) * main
+        fb = (rng.uniform(size=n) < 0.5) * bkg
+        triples.append((len(cols), len(cols) + 1, len(cols) + 2))
+        cols += [fa, fb, fa + fb]
+    Gc = np.stack(cols, axis=1)
+    kk = Gc.sum(axis=0)
+    S3 = np.zeros((Gc.shape[1], 3))
+    S3[:, 0] = kk * (kk - 1)                                   # sum_{i != j} G_ic G_jc
+    for q in range(2):                                         # sum_{i != j} G_iq G_jc
+        S3[:, 1 + q] = kk[q] * kk - Gc[:, q] @ Gc
+    for (ca, cb, cg) in triples:
+        nx, nxb = int(kk[ca]), nm - int(kk[ca])
+        bx, bxb = int(kk[cb]), n - nm - int(kk[cb])
+        T3 = tp.energy_eq3(S3, 0, 1, 0, 1, [(ca, cb, cg)], nx, nxb, bx, bxb, 0.3 * nx, 0.3 * nxb)
+        assert abs(T3[0]) < 1e-12

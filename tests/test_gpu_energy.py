@@ -218,3 +218,29 @@ def test_coords_d4pi_exact_ties(tp):
         rows.append([[E1, a, 0, 0], [E2, 0, b, 0], [E1, -a, 0, 0], [E2, 0, -b, 0]])
     comps = np.array(rows, dtype=np.float32).transpose(1, 2, 0).copy()
     _d4pi_check(tp, comps, "ties")
+
+
+@pytest.mark.parametrize("C,nrow,n", [(32, 0, 1500), (64, 1, 2051), (64, 3, 1729), (128, 2, 2051), (128, 3, 1300)])
+def test_raw_pair_sums_all_tile_counts(tp, C, nrow, n):
+    """sums[c][0] = sum_{i != j} G_ic psi_ij G_jc and sums[c][1+q] = sum_{i != j} G_iq psi_ij G_jc
+    against the dense float64 psi matrix, for every column-tile count and row-weight count
+    (ragged n: several workgroup pieces and a partial last block)."""
+    ch, s = sample(n, 200 + C + nrow)
+    ds = tp.DeviceSample.from_sample(s)
+    Yg = tp.coords(ds, MASKS, 1e-3)
+    rng = np.random.default_rng(C + nrow)
+    G = (rng.uniform(size=(n, C)) < rng.uniform(0.1, 0.9, size=C)).astype(np.uint8)
+    sums = tp.pairsums(Yg, torch.from_numpy(G).cuda(), 0.35, nrow=nrow)
+    torch.cuda.synchronize()
+    S = sums.cpu().numpy()
+    comps, _ = s.numpy()
+    Yo = energy.invariant_masses(comps, MASKS) * 1e-3
+    Psi = energy.psi_block(Yo, Yo, 0.35)
+    np.fill_diagonal(Psi, 0.0)
+    Gf = G.astype(np.float64)
+    V = Psi @ Gf                                  # [n][C]
+    want0 = np.einsum("ic,ic->c", Gf, V)
+    assert np.all(np.abs(S[:, 0] - want0) <= 1e-5 * want0 + 1e-9)
+    for q in range(nrow):
+        wq = Gf[:, q] @ V                         # sum_i G_iq (Psi G)_ic
+        assert np.all(np.abs(S[:, 1 + q] - wq) <= 1e-5 * wq + 1e-9), q
