@@ -287,8 +287,8 @@ def main():
                     help="also run a plain 1 GiB device copy (reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the pass shards by events with one uint64 histogram all-reduce; see DESIGN.md)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the pass would shard by events and sum the uint64 histograms with one all-reduce)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -48,7 +48,7 @@ extern "C" {
 typedef enum {
     TP_OK = 0,
     TP_EINVAL = -1,        /* bad argument (null pointer, size, slot, edges ...) */
-    TP_EUNSUPPORTED = -2,  /* valid request this build does not support          */
+    TP_EUNSUPPORTED = -2,  /* valid request the library does not support         */
     TP_EHIP = -3,          /* a HIP runtime call failed                           */
     TP_ENOMEM = -4,        /* device allocation failed                            */
     TP_ERANGE = -5,        /* a size exceeds an implementation limit              */
