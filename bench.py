@@ -111,7 +111,7 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 MFMA_F16_PEAK_TFLOPS = 2500.0   # dense float16 matrix-core peak
 
 
-def energy_leg(n, nperm, dev, per_pass=126):
+def energy_leg(n, nperm, dev, per_pass=126, cpu_events=0):
     """The energy test at the paper's scale: D0 -> K+ K- pi+ pi- events, five
     invariant-mass coordinates, the P-odd split ([I+IV] vs [II+III]) and
     ``nperm`` permutations of it, ``per_pass`` of them per launch of the pair
@@ -172,7 +172,25 @@ def energy_leg(n, nperm, dev, per_pass=126):
     C0 = colsets[0].shape[1]
     log(f"energy test: {n} events, {nperm} permutations in {len(ks)} launches of {C0} columns, "
         f"{sec * 1e3:.1f} ms, {sec * 1e3 / nperm:.2f} ms per permutation, T = {T_obs:.4e}")
-    return {"events": n, "coordinates": 5, "sigma_GeV": sigma, "columns": C0, "permutations": nperm,
+    cpu = None
+    if cpu_events > 0:
+        # the oracle (plain float64 pair sums, numpy) on the first cpu_events
+        # events of the same coordinates: one T of eq. (2) = every ordered pair once
+        from oracle import energy
+        m = int(cpu_events)
+        Yh = Y[:, :m].double().cpu().numpy()
+        lh = lab[:m].cpu().numpy()
+        t0 = time.perf_counter()
+        energy.T_eq2(Yh, lh, sigma)
+        csec = time.perf_counter() - t0
+        rate = m * (m - 1) / csec
+        cpu = {"value": rate, "unit": "ordered pairs/s", "cores": 1, "kind": "oracle",
+               "sample": f"T of eq. (2) for the observed split of the first {m} events (float64 numpy, one thread)",
+               "seconds": csec,
+               "seconds_per_permutation_at_full_size": n * (n - 1) / rate}
+        log(f"energy oracle: {rate:.3e} ordered pairs/s ({csec:.1f} s for {m} events); "
+            f"one permutation at {n} events ~{n * (n - 1) / rate:.0f} s")
+    return {"cpu_baseline": cpu,"events": n, "coordinates": 5, "sigma_GeV": sigma, "columns": C0, "permutations": nperm,
             "launches": len(ks), "seconds": sec, "seconds_per_pass": sec / len(ks),
             "ms_per_permutation": sec * 1e3 / nperm,
             "unordered_pairs_per_s": pairs * len(ks) / sec,
@@ -281,6 +299,8 @@ def main():
                     help="permutations of the energy-test leg, 126 per launch of 128 columns")
     ap.add_argument("--no-ordered", action="store_true",
                     help="skip the leg that repeats the pass with the identical particles ordered on the fly")
+    ap.add_argument("--energy-cpu-events", type=float, default=8000,
+                    help="events of the bounded oracle timing beside the energy-test leg")
     ap.add_argument("--energy-bkg-perms", type=int, default=164,
                     help="permutations of the background-subtracted (eq. 3) leg, 41 per launch (0 skips it)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -455,7 +475,8 @@ def main():
         out["parity_vs_oracle"] = {"samples_checked": len(orc), "counts_bit_exact": bool(ok)}
         log(f"cpu baseline {cpu['value']:.3e} events/s on {cpu['cores']} threads ({cpu['seconds']:.1f}s)")
     if args.energy_events > 0:
-        out["energy_test"] = energy_leg(int(args.energy_events), args.energy_perms, dev)
+        out["energy_test"] = energy_leg(int(args.energy_events), args.energy_perms, dev,
+                                        cpu_events=0 if args.no_cpu else args.energy_cpu_events)
         if args.energy_bkg_perms > 0:
             out["energy_test_background"] = energy_bkg_leg(int(args.energy_events), args.energy_bkg_perms, dev)
     print(json.dumps(out), flush=True)
