@@ -208,6 +208,15 @@ def test_coords_d4pi_relabel_matches_oracle(tp):
     _d4pi_check(tp, shuffled, "shuffled pions")
 
 
+def test_coords_d4pi_float64_storage(tp):
+    ch = synth.CHANNELS["D0_pipipipi"]
+    comps, _ = synth.generate(ch, 2001, 83, dtype=torch.float64).numpy()
+    k = np.random.default_rng(5).integers(0, 4, size=comps.shape[2])
+    perms = np.array(energy.D4PI_PERMS)[k]
+    idx = np.arange(comps.shape[2])
+    _d4pi_check(tp, np.stack([comps[perms[:, t], :, idx].T for t in range(4)]), "float64 storage")
+
+
 def test_coords_d4pi_exact_ties(tp):
     # small-integer events with tied pair masses (exact path, stored-order ties)
     rng = np.random.default_rng(6)
@@ -220,7 +229,8 @@ def test_coords_d4pi_exact_ties(tp):
     _d4pi_check(tp, comps, "ties")
 
 
-@pytest.mark.parametrize("C,nrow,n", [(32, 0, 1500), (64, 1, 2051), (64, 3, 1729), (128, 2, 2051), (128, 3, 1300)])
+@pytest.mark.parametrize("C,nrow,n", [(32, 0, 1500), (64, 1, 2051), (64, 3, 1729), (128, 2, 2051), (128, 3, 1300),
+                                      (32, 1, 2), (32, 1, 3), (64, 2, 127), (32, 3, 129), (128, 1, 300)])
 def test_raw_pair_sums_all_tile_counts(tp, C, nrow, n):
     """sums[c][0] = sum_{i != j} G_ic psi_ij G_jc and sums[c][1+q] = sum_{i != j} G_iq psi_ij G_jc
     against the dense float64 psi matrix, for every column-tile count and row-weight count

@@ -30,9 +30,9 @@ def u64(t):
     return t.cpu().numpy().view(np.uint64).astype(object)
 
 
-def shuffled(name, n, seed):
+def shuffled(name, n, seed, dtype=torch.float32):
     ch = synth.CHANNELS[name]
-    s = synth.generate(ch, n, seed, inj=synth.INJ_SIN)
+    s = synth.generate(ch, n, seed, inj=synth.INJ_SIN, dtype=dtype)
     mask = torch.from_numpy(np.random.default_rng(seed).uniform(size=n) < 0.5)
     for c in range(4):
         a, b = s.comps[1][c].clone(), s.comps[3][c].clone()
@@ -106,3 +106,13 @@ def test_exact_ties_keep_stored_order(tp):
         print(f"[order] ties prec={prec} stats={stats}", flush=True)
         assert stats[5] > 0                     # the ties went to the exact tier
         assert counts == want["counts"]
+
+
+def test_float64_storage(tp):
+    ch, s = shuffled("Lb_pKKK", 30011, 29, dtype=torch.float64)
+    axes = SCHEMES["abscos_slow_x_phi"]
+    comps, tag = s.numpy()
+    want = oracle.run(comps, tag, ch.triple, ch.planes, axes, identical=IDENT)
+    counts, stats = gpu_counts(tp, s, ch, axes, tp.TP_PREC_F64)
+    assert stats[6] == 0
+    assert counts == want["counts"] and stats[:4] == want["stats"]
