@@ -299,7 +299,7 @@ def main():
                     help="permutations of the energy-test leg, 126 per launch of 128 columns")
     ap.add_argument("--no-ordered", action="store_true",
                     help="skip the leg that repeats the pass with the identical particles ordered on the fly")
-    ap.add_argument("--energy-cpu-events", type=float, default=8000,
+    ap.add_argument("--energy-cpu-events", type=float, default=30000,
                     help="events of the bounded oracle timing beside the energy-test leg")
     ap.add_argument("--energy-bkg-perms", type=int, default=164,
                     help="permutations of the background-subtracted (eq. 3) leg, 41 per launch (0 skips it)")

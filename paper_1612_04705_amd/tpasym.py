@@ -134,6 +134,14 @@ def _stream(stream):
 
 
 # ------------------------------------------------------------------ descriptors
+def _on_one_gpu(*tensors):
+    """Every tensor a CUDA (ROCm) tensor on one device: the kernels take raw device
+    pointers, so host memory or a second device must be refused here."""
+    devs = {t.device for t in tensors}
+    if len(devs) != 1 or not next(iter(devs)).type == "cuda":
+        raise TPError("tensors must all live on one GPU device")
+
+
 @dataclass
 class DeviceSample:
     """16 component tensors (slot-major [s][c]) and the int8 tag tensor on one device."""
@@ -162,6 +170,7 @@ class DeviceSample:
             e.p[k] = t.data_ptr()
         if self.tag.dtype != torch.int8:
             raise TPError("tag must be int8")
+        _on_one_gpu(self.tag, *self.comps)
         e.tag = self.tag.data_ptr()
         return e
 
@@ -207,6 +216,13 @@ def new_counts(binning: Binning, device="cuda"):
             torch.zeros(8, dtype=torch.int64, device=device))
 
 
+def _check_counts(bn: Binning, counts, stats, ds: DeviceSample):
+    if (counts.dtype != torch.int64 or not counts.is_contiguous() or counts.numel() != bn.nrows * 4
+            or stats.dtype != torch.int64 or not stats.is_contiguous() or stats.numel() != 8):
+        raise TPError("counts must be contiguous int64 [(nbins + 1) * 4] and stats int64 [8]")
+    _on_one_gpu(counts, stats, ds.tag)
+
+
 # ------------------------------------------------------------------ entry points
 def compute(ds: DeviceSample, ch: _Channel, precision=TP_PREC_F64, want_ct=True, stats=None, stream=None):
     """tp_compute: per-event class (int8) and C_T^inv (float64) on the device."""
@@ -216,6 +232,9 @@ def compute(ds: DeviceSample, ch: _Channel, precision=TP_PREC_F64, want_ct=True,
     ct = torch.empty(ds.n, dtype=torch.float64, device=ds.tag.device) if want_ct else None
     if stats is None:
         stats = torch.zeros(8, dtype=torch.int64, device=ds.tag.device)
+    if stats.dtype != torch.int64 or not stats.is_contiguous() or stats.numel() != 8:
+        raise TPError("stats must be contiguous int64 [8]")
+    _on_one_gpu(stats, ds.tag)
     _check(lib.tp_compute(ctypes.byref(ev), ctypes.byref(ch), int(precision), ctypes.c_void_p(cls.data_ptr()),
                           ctypes.c_void_p(ct.data_ptr()) if ct is not None else None,
                           ctypes.c_void_p(stats.data_ptr()), _stream(stream)))
@@ -229,6 +248,7 @@ def bin(ds: DeviceSample, ch: _Channel, bn: Binning, precision=TP_PREC_F64, coun
     ev = ds.events()
     if counts is None or stats is None:
         counts, stats = new_counts(bn, ds.tag.device)
+    _check_counts(bn, counts, stats, ds)
     _check(lib.tp_bin(ctypes.byref(ev), ctypes.byref(ch), ctypes.byref(bn.b), int(precision),
                       ctypes.c_void_p(counts.data_ptr()), ctypes.c_void_p(stats.data_ptr()), _stream(stream)))
     return counts, stats
@@ -242,6 +262,7 @@ class Batch:
         self.items = list(items)
         self.arr = (_Sample * len(self.items))()
         for i, (ds, ch, bn, counts, stats) in enumerate(self.items):
+            _check_counts(bn, counts, stats, ds)
             self.arr[i].ev = ds.events()
             self.arr[i].ch = ch
             self.arr[i].bn = bn.b
@@ -317,7 +338,11 @@ def coords(ds: DeviceSample, masks, scale=1e-3, out=None, stream=None, relabel=T
     m = (ctypes.c_int32 * len(masks))(*masks)
     if out is None:
         out = torch.empty((len(masks), ds.n), dtype=torch.float32, device=ds.tag.device)
+    if (out.dtype != torch.float32 or out.dim() != 2 or out.shape[0] != len(masks) or out.shape[1] < ds.n
+            or out.stride(1) != 1):
+        raise TPError("out must be float32 [len(masks)][>= n] with unit inner stride")
     e = ds.events()
+    _on_one_gpu(out, ds.tag)
     _check(load().tp_coords(ctypes.byref(e), m, len(masks), float(scale), int(relabel),
                             ctypes.c_void_p(out.data_ptr()), out.stride(0), _stream(stream)))
     return out
@@ -329,9 +354,14 @@ def pairsums(Y, cols, sigma, nrow=1, sums=None, stream=None):
     the device); returns float64 [C][1 + nrow] (accumulated)."""
     if Y.dtype != torch.float32 or cols.dtype != torch.uint8 or not cols.is_contiguous() or Y.stride(1) != 1:
         raise TPError("Y must be float32 with unit inner stride, cols contiguous uint8")
+    if Y.dim() != 2 or cols.dim() != 2 or Y.shape[1] < cols.shape[0]:
+        raise TPError("Y must be [D][>= n] and cols [n][C]")
     n, C = cols.shape
     if sums is None:
         sums = torch.zeros((C, 1 + nrow), dtype=torch.float64, device=cols.device)
+    if sums.dtype != torch.float64 or tuple(sums.shape) != (C, 1 + nrow) or not sums.is_contiguous():
+        raise TPError("sums must be contiguous float64 [C][1 + nrow]")
+    _on_one_gpu(Y, cols, sums)
     _check(load().tp_pairsums(ctypes.c_void_p(Y.data_ptr()), Y.shape[0], Y.stride(0), n, float(sigma),
                               ctypes.c_void_p(cols.data_ptr()), C, int(nrow),
                               ctypes.c_void_p(sums.data_ptr()), _stream(stream)))

@@ -224,3 +224,20 @@ def test_energy_host_forms_vanish_when_psi_is_one(tp):
         bx, bxb = int(kk[cb]), n - nm - int(kk[cb])
         T3 = tp.energy_eq3(S3, 0, 1, 0, 1, [(ca, cb, cg)], nx, nxb, bx, bxb, 0.3 * nx, 0.3 * nxb)
         assert abs(T3[0]) < 1e-12
+
+
+def test_binding_refuses_host_tensors(tp):
+    # the kernels take raw device pointers: host memory must be refused by the binding
+    import torch
+    from paper_1612_04705_amd import synth
+    s = synth.generate(synth.CHANNELS["D0_KKpipi"], 64, 1)
+    ds = tp.DeviceSample([s.comps[a][b] for a in range(4) for b in range(4)], s.tag)   # host tensors
+    with pytest.raises(tp.TPError):
+        ds.events()
+    with pytest.raises(tp.TPError):
+        tp.pairsums(torch.zeros((5, 64)), torch.zeros((64, 32), dtype=torch.uint8), 0.3)
+    with pytest.raises(tp.TPError):      # Y narrower than the columns
+        tp.pairsums(torch.zeros((5, 10)), torch.zeros((64, 32), dtype=torch.uint8), 0.3)
+    with pytest.raises(tp.TPError):      # wrong sums shape
+        tp.pairsums(torch.zeros((5, 64)), torch.zeros((64, 32), dtype=torch.uint8), 0.3,
+                    sums=torch.zeros((32, 3), dtype=torch.float64))
