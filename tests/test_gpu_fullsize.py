@@ -1,0 +1,93 @@
+"""Parity at the workloads' full sizes (1e5 ... 5e8 events), in the launch
+configuration the benchmark times (batched, HIP graph, tuned shapes).
+
+The oracle cannot decide 5e8 events, so at full size the checks are
+* properties that hold at any size: the float32-recheck path, the plain
+  float64 path and the batched graph path give bit-identical counts and
+  statistics; row 0 of the counts totals the classified events; every event is
+  counted once;
+* sampled outputs the oracle computes one by one: the per-event classes of
+  4096 randomly chosen events (tp_compute on the whole sample) against the
+  oracle on exactly those events.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1612_04705_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tp():
+    from paper_1612_04705_amd import tpasym
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    tpasym.load()
+    return tpasym
+
+
+def u64(t):
+    return [int(x) for x in t.cpu().numpy().view(np.uint64)]
+
+
+@pytest.mark.parametrize("workload", ["lb_ppipipi_f64_1e5", "lb_ppipipi_1e7_phi12", "lb_pkpipi_1e8_phi10xm8",
+                                      "d0_kkpipi_5e8_m32x32"])
+def test_full_size(tp, workload):
+    dev = torch.device("cuda:0")
+    (spec,) = synth.workload_specs(workload, 1.0)
+    s = synth.make_sample(spec, device=dev)
+    s.phi_gen = s.gamma = s.m12 = s.m34 = None
+    torch.cuda.empty_cache()
+    n = s.n
+    print(f"[full] {workload}: {n} events generated", flush=True)
+    ds = tp.DeviceSample([s.comps[a][b] for a in range(4) for b in range(4)], s.tag)
+    ch = tp.channel(spec.channel.triple, spec.channel.planes)
+    bn = tp.Binning(spec.axes)
+    f32 = spec.dtype == torch.float32
+    results = []
+    for prec in ([tp.TP_PREC_F32_RECHECK] if f32 else []) + [tp.TP_PREC_F64]:
+        counts, stats = tp.bin(ds, ch, bn, prec)
+        torch.cuda.synchronize()
+        results.append((prec, u64(counts), u64(stats)))
+    # the benchmark's launch configuration: batched, tuned shapes, HIP graph, three steps
+    counts, stats = tp.new_counts(bn)
+    b = tp.Batch([(ds, ch, bn, counts, stats)])
+    prec = tp.TP_PREC_F32_RECHECK if f32 else tp.TP_PREC_F64
+    b.autotune(prec)
+    counts.zero_()
+    stats.zero_()
+    for _ in range(3):
+        b.run(prec, None, True)
+    torch.cuda.synchronize()
+    c3, s3 = u64(counts), u64(stats)
+    results.append((prec, [v // 3 for v in c3], [v // 3 for v in s3]))
+    assert all(v % 3 == 0 for v in c3 + s3)
+    # counts and the event statistics agree everywhere; the tier statistics
+    # (float64 rechecks of float32 signs, listed events) only within one precision
+    for pr, c_, st_ in results[1:]:
+        assert c_ == results[0][1]
+        assert st_[:4] == results[0][2][:4] and st_[6] == results[0][2][6]
+        same = [r for r in results if r[0] == pr]
+        assert all(r[2] == same[0][2] for r in same)
+    _, c, st = results[0]
+    assert st[6] == 0                                   # nothing unresolved
+    assert st[0] == n
+    assert sum(c[:4]) == n - st[1] - st[2]              # row 0: every classified event once
+    if bn.nrows > 1:
+        binned = np.array(c[4:]).reshape(-1, 4).sum(axis=0)
+        assert int(binned.sum()) == sum(c[:4]) - st[3]  # in range or counted out of range
+    print(f"[full] {workload}: counts equal across paths, tier2={st[4]} tier3={st[5]}", flush=True)
+
+    # sampled per-event classes against the oracle
+    cls, _, _ = tp.compute(ds, ch, prec, want_ct=False)
+    torch.cuda.synchronize()
+    idx = torch.from_numpy(np.sort(np.random.default_rng(11).choice(n, 4096, replace=False))).to(dev)
+    comps = np.stack([s.comps[a][b].index_select(0, idx).cpu().numpy() for a in range(4) for b in range(4)])
+    comps = comps.reshape(4, 4, -1)
+    tag = s.tag.index_select(0, idx).cpu().numpy()
+    want = oracle.run(comps, tag, spec.channel.triple, spec.channel.planes, want_events=True)
+    assert np.array_equal(cls.index_select(0, idx).cpu().numpy(), want["cls"])
+    del ds, s, b
+    torch.cuda.empty_cache()
