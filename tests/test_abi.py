@@ -241,3 +241,22 @@ def test_binding_refuses_host_tensors(tp):
     with pytest.raises(tp.TPError):      # wrong sums shape
         tp.pairsums(torch.zeros((5, 64)), torch.zeros((64, 32), dtype=torch.uint8), 0.3,
                     sums=torch.zeros((32, 3), dtype=torch.float64))
+
+
+def test_energy_eq2_degenerate_samples_give_nan(tp):
+    # a column whose sample or complement has fewer than two events has no T
+    n = 10
+    S = np.ones((4, 2))
+    nx = np.array([n, 1, n - 1, 5])          # all ones (complement empty), one event, one left out, fine
+    T = tp.energy_eq2(S, nx, n)
+    assert np.isnan(T[0]) and np.isnan(T[1]) and np.isnan(T[2]) and not np.isnan(T[3])
+    # bad indices are refused
+    lib = tp.load()
+    P = ctypes.POINTER
+    Sc = np.ascontiguousarray(S)
+    nxc = np.ascontiguousarray(nx.astype(np.int64))
+    out = np.zeros(4)
+    assert lib.tp_energy_eq2(Sc.ctypes.data_as(P(ctypes.c_double)), 4, 1, 1, 0,
+                             nxc.ctypes.data_as(P(ctypes.c_int64)), n, out.ctypes.data_as(P(ctypes.c_double))) == -1
+    assert lib.tp_energy_eq2(Sc.ctypes.data_as(P(ctypes.c_double)), 4, 1, 0, 4,
+                             nxc.ctypes.data_as(P(ctypes.c_int64)), n, out.ctypes.data_as(P(ctypes.c_double))) == -1
