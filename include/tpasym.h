@@ -297,12 +297,16 @@ int tp_coords(const tp_events *ev, const int32_t *masks, int32_t ncoord, double 
  * cols [n][ncols] uint8 0/1 (device, row-major, 16-byte aligned, ncols 32, 64
  * or 128; its first nrow (0..3) columns are also the row weights); sums
  * [ncols][1 + nrow] float64 (device, accumulated: zero it once).  sigma > 0.
- * psi is formed in float32 (hardware exp2) for pairs j > i only (psi is
- * symmetric) and enters the matrix cores as two float16 terms (truncation of
- * psi * 2^14 and of the remainder: together within 2^-20 of psi, relative);
- * the 0/1 columns are exact in float16, products are accumulated in float32
- * over 1024 j and then in float64.  Sums are accurate to ~1e-5 relative
- * (typically ~1e-6).  Async on ``stream``. */
+ * psi is formed for pairs j > i only (psi is symmetric): the squared
+ * distance as a float32 dot product of (coordinates - centre, squared norm)
+ * vectors on the matrix cores (centre: mean of the first 256 events; rounding
+ * grows with the squared distance of the events from it), then the hardware
+ * exp2.  psi enters the matrix cores again as two float16 terms (truncation
+ * of psi * 2^14 and of the remainder: together within 2^-20 of psi,
+ * relative); the 0/1 columns are exact in float16, products are accumulated
+ * in float32 over 1024 j and then in float64.  Sums are accurate to ~1e-5
+ * relative (typically ~1e-6) for coordinates whose spread is a few sigma.
+ * Async on ``stream``. */
 int tp_pairsums(const float *coords, int32_t dims, int64_t ld, int64_t n, double sigma, const uint8_t *cols,
                 int32_t ncols, int32_t nrow, double *sums, void *stream);
 

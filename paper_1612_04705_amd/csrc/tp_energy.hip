@@ -14,19 +14,29 @@
 // sum w_i psi_ij G_jc plus the transposed term sum_i G_ic (Psi_upper w_q)_i,
 // where (Psi_upper w_q) is column q of the same product.
 //
-// V = Psi G is a dense contraction over j, done on the matrix cores in half
-// precision with float32 accumulation (v_mfma_f32_32x32x16_f16).  psi is
-// formed in float32 (VALU: distance, exp2), scaled by 2^14 (exact) and split
-// into two float16 terms hi = rtz(psi), lo = rtz(psi - hi): the difference is
-// exact in float32 and hi + lo is within 2^-20 (relative, from below) of the
-// float32 psi; the scale keeps both terms clear of the float16 subnormals for
-// every psi above 2^-17.  The 0/1 columns are exact in float16, so each product
-// is exact and only the float32 accumulation rounds.  A lane forms 8 psi per
-// step, for its row and 8 consecutive j; the matrix core multiplies the
-// 32 x 16 tile of hi (then lo) by the 16 x 32 column tile.  Columns are staged
-// in LDS transposed ([c][j], float16), so a lane's 8 values of one column are
-// one 16-byte read.  Every FL chunks the float32 tiles are reduced per column
-// into float64 partials, so float32 only sums 2 * FL * JC products.
+// Both steps run on the matrix cores.  Distances: with the scaled coordinates
+// centred on the mean c of the first 256 events, v = y yscale - c, the vectors
+// x_j = (v_j, |v_j|^2, 1) and x_i = (-2 v_i, 1, |v_i|^2 - 14) give
+// x_i . x_j = |v_i - v_j|^2 - 14, a float32 contraction over D + 2 components
+// (v_mfma_f32_32x32x2_f32), so psi * 2^14 = 2^-(x_i . x_j) costs one exp2 per
+// pair on the vector ALU.  Rounding of that dot product is bounded by about
+// (D + 10) 2^-24 (2 |v_i|^2 + 2 |v_j|^2 + 14); centring keeps the |v|^2 small
+// (a few units for invariant masses at sigma ~ 0.3 GeV), which puts psi within
+// ~2e-6 (relative, random sign) of the value for the same float32 coordinates.
+// V = Psi G is then a dense contraction over j in half precision with float32
+// accumulation (v_mfma_f32_32x32x16_f16): psi * 2^14 is split into two float16
+// terms hi = rtz(psi), lo = rtz(psi - hi): the difference is exact in float32
+// and hi + lo is within 2^-20 (relative, from below) of the float32 psi; the
+// scale keeps both terms clear of the float16 subnormals for every psi above
+// 2^-17.  The 0/1 columns are exact in float16, so each product is exact and
+// only the float32 accumulation rounds.  The distance tile of 32 rows x 32 j
+// leaves each lane 16 psi of its row, which are the lane's half of two 32 x 16
+// operand tiles; columns are staged in LDS transposed ([c][j], float16, in the
+// j order those tiles use), so a lane's 8 values of one column are one 16-byte
+// read.  The next chunk's columns and coordinates are loaded into registers
+// while the current one is multiplied.  Every FL chunks the float32 tiles are
+// reduced per column into float64 partials, so float32 only sums 2 * FL * JC
+// products.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -49,26 +59,50 @@ constexpr int JC = 128;       // j per LDS chunk
 constexpr int KS = 16;        // j per matrix-core step
 constexpr int FL = 8;         // chunks per float32 -> float64 reduction
 constexpr int GPAD = 8;       // float16 padding per staged column (spreads LDS banks)
-constexpr float PSI_SCALE = 16384.0f;         // 2^14
+constexpr float PSI_LOG2 = 14.0f;             // psi is formed scaled by 2^14
 constexpr double PSI_UNSCALE = 1.0 / 16384.0;
 
 template <int NT>
 struct Smem {
     static constexpr int C = 32 * NT;
-    float ys[MAXD][JC];                 // coordinates of the chunk, [d][j], scaled by yscale
+    float xs[MAXD + 2][JC];             // chunk j vectors, [k][j]: y_j - c (D), |y_j - c|^2, 1, zeros
+    float cw[4][MAXD];                  // per-wave coordinate sums for the centre c
     uint16_t gs[C][JC + GPAD];          // columns of the chunk, [c][j], float16 0 or 1
     uint8_t gi[ROWS * C];               // columns of this block's rows, [i][c]
     float rw[ROWS][8];                  // per row: weights G[i][q] (0..2), (Psi_upper G)[i][q] (4..6)
     double red[C][1 + MAXR];            // workgroup totals
 };
 
+// Centre c of the scaled coordinates: the mean of the first min(n, 256)
+// events, formed in a fixed order so that every workgroup gets the same bits.
+template <int NT>
+__device__ __forceinline__ void centre(const EParams &p, Smem<NT> &sm, float (&c)[MAXD])
+{
+    const int tid = threadIdx.x;
+    const int64_t m = p.n < 256 ? p.n : 256;
+#pragma unroll
+    for (int d = 0; d < MAXD; ++d) {
+        float x = (d < p.D && tid < m) ? p.Y[d * p.ldY + tid] * p.yscale : 0.0f;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) x += __shfl_xor(x, o);
+        if ((tid & 63) == 0) sm.cw[tid >> 6][d] = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int d = 0; d < MAXD; ++d) c[d] = ((sm.cw[0][d] + sm.cw[1][d]) + (sm.cw[2][d] + sm.cw[3][d])) / (float)(m > 0 ? m : 1);
+}
+
 // Row block setup: columns and row weights of rows ib .. ib + ROWS - 1, and
-// this lane's row coordinates (scaled by yscale, so psi = 2^-(scaled distance)^2).
-template <int NT, int DP>
-__device__ __forceinline__ void setup_rows(const EParams &p, Smem<NT> &sm, int64_t ib, float (&yi)[DP])
+// this lane's entries of its row's vector x_i = (-2 (y_i - c), 1,
+// |y_i - c|^2 - 14) (scaled coordinates, so psi = 2^-(scaled distance)^2):
+// x_i . x_j = |y_i - y_j|^2 - 14 for the chunk vectors x_j.  Lane half h
+// holds components 2 s + h, s < NS.
+template <int NT, int NS>
+__device__ __forceinline__ void setup_rows(const EParams &p, Smem<NT> &sm, int64_t ib, const float (&c)[MAXD], float (&xi)[NS])
 {
     constexpr int C = 32 * NT;
     const int tid = threadIdx.x;
+    const int h = (tid >> 5) & 1;
     const int64_t i = ib + (tid >> 6) * 32 + (tid & 31);
     __syncthreads();
     for (int e = tid; e < ROWS * C / 16; e += 256) {
@@ -85,83 +119,138 @@ __device__ __forceinline__ void setup_rows(const EParams &p, Smem<NT> &sm, int64
 #pragma unroll
         for (int q = 3; q < 8; ++q) sm.rw[tid][q] = 0.0f;
     }
+    float x[2 * NS];
+    float nrm = 0.0f;
 #pragma unroll
-    for (int d = 0; d < DP; ++d) yi[d] = (d < p.D && i < p.n) ? p.Y[d * p.ldY + i] * p.yscale : 0.0f;
+    for (int k = 0; k < 2 * NS; ++k) x[k] = 0.0f;
+#pragma unroll
+    for (int d = 0; d < 2 * NS - 2; ++d) {
+        const float v = (d < p.D && i < p.n) ? p.Y[d * p.ldY + i] * p.yscale - c[d] : 0.0f;
+        nrm = fmaf(v, v, nrm);
+        if (d < p.D) x[d] = -2.0f * v;
+    }
+#pragma unroll
+    for (int k = 0; k < 2 * NS; ++k) {
+        if (k == p.D) x[k] = 1.0f;
+        if (k == p.D + 1) x[k] = nrm - PSI_LOG2;
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) xi[s] = h ? x[2 * s + 1] : x[2 * s];
 }
 
-// Stage chunk j0 .. j0 + JC - 1: coordinates [d][j], and the columns transposed
-// to [c][j] as float16.  Each item takes 4 rows x 16 columns (four 16-byte
-// loads) and writes, per column, the 4 rows as one 8-byte word: bytes b of two
-// rows are placed as the 16-bit lanes of one word (b0 | b1 << 16), and the
-// 24-bit multiply by 0x3C00 turns each lane's 0/1 into float16 0 or 1.0.
-template <int NT, int DP>
-__device__ __forceinline__ void stage_chunk(const EParams &p, Smem<NT> &sm, int64_t j0)
+// Position of local j in a staged column: bits 2 and 3 swapped, the order in
+// which the distance tiles deliver psi to the matrix-core operand (see
+// chunk_products).
+__device__ __forceinline__ int swap23(int j) { return (j & ~12) | ((j & 4) << 1) | ((j & 8) >> 1); }
+
+// Stage chunk j0 .. j0 + JC - 1: the vectors x_j = (y_j - c, |y_j - c|^2, 1)
+// as [k][j] (padding events j >= n get y_j = c, so every psi stays finite; their
+// columns are 0), and the columns transposed to [c][swap23(j)] as float16.
+// Each item takes 4 rows x 16 columns (four 16-byte loads) and writes, per
+// column, the 4 rows as one 8-byte word: bytes b of two rows are placed as the
+// 16-bit lanes of one word (b0 | b1 << 16), and the 24-bit multiply by 0x3C00
+// turns each lane's 0/1 into float16 0 or 1.0.
+// One chunk in flight in registers: thread tid < JC holds the coordinates of
+// event j0 + tid, thread it < ITEMS the 4 rows x 16 columns of its item.  The
+// loads for chunk v + 1 are issued before chunk v is multiplied and written to
+// LDS after it, so their latency hides behind the products.
+template <int KA>
+struct Pending {
+    float y[KA - 2];
+    u32x4 w[4];
+};
+
+template <int NT, int KA>
+__device__ __forceinline__ void load_chunk(const EParams &p, int64_t j0, Pending<KA> &pd)
 {
     constexpr int C = 32 * NT;
-    constexpr int CG = C / 16;
-    constexpr int ITEMS = (JC / 4) * CG;
+    constexpr int ITEMS = (JC / 4) * (C / 16);
+    static_assert(ITEMS <= 256, "one item per thread");
+    const int tid = threadIdx.x;
+    const int64_t j = j0 + tid;
+#pragma unroll
+    for (int d = 0; d < KA - 2; ++d) pd.y[d] = (tid < JC && d < p.D && j < p.n) ? p.Y[d * p.ldY + j] : 0.0f;
+    const int jq = (tid % (JC / 4)) * 4;
+    const int cg = tid / (JC / 4);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        const int64_t jr = j0 + jq + rr;
+        pd.w[rr] = (tid < ITEMS && jr < p.n) ? *reinterpret_cast<const u32x4 *>(p.G + jr * C + 16 * cg) : u32x4{ 0u, 0u, 0u, 0u };
+    }
+}
+
+template <int NT, int KA>
+__device__ __forceinline__ void store_chunk(const EParams &p, Smem<NT> &sm, int64_t j0, const Pending<KA> &pd,
+                                            const float (&c)[MAXD])
+{
+    constexpr int C = 32 * NT;
+    constexpr int ITEMS = (JC / 4) * (C / 16);
     const int tid = threadIdx.x;
     if (tid < JC) {
-        const int64_t j = j0 + tid;
+        const bool real = j0 + tid < p.n;   // padding events sit at the centre
+        float nrm = 0.0f;
 #pragma unroll
-        for (int d = 0; d < DP; ++d) sm.ys[d][tid] = (d < p.D && j < p.n) ? p.Y[d * p.ldY + j] * p.yscale : 0.0f;
-    }
-    for (int it = tid; it < ITEMS; it += 256) {
-        const int jq = (it % (JC / 4)) * 4;
-        const int cg = it / (JC / 4);
-        u32x4 w[4];
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-            const int64_t j = j0 + jq + rr;
-            w[rr] = j < p.n ? *reinterpret_cast<const u32x4 *>(p.G + j * C + 16 * cg) : u32x4{ 0u, 0u, 0u, 0u };
+        for (int d = 0; d < KA - 2; ++d) {
+            const float v = (d < p.D && real) ? pd.y[d] * p.yscale - c[d] : 0.0f;
+            nrm = fmaf(v, v, nrm);
+            if (d < p.D) sm.xs[d][tid] = v;
         }
+#pragma unroll
+        for (int k = 0; k < KA; ++k) {
+            if (k == p.D) sm.xs[k][tid] = nrm;
+            else if (k == p.D + 1) sm.xs[k][tid] = 1.0f;
+            else if (k > p.D + 1) sm.xs[k][tid] = 0.0f;
+        }
+    }
+    if (tid < ITEMS) {
+        const int jq = (tid % (JC / 4)) * 4;
+        const int cg = tid / (JC / 4);
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int m = q & 3, wd = q >> 2;
             // byte m of the second source (first row of the pair) to bits 0..7,
             // byte m of the first source (second row) to bits 16..23, zeros elsewhere
             const uint32_t sel = (uint32_t)m | (0x0cu << 8) | ((uint32_t)(4 + m) << 16) | (0x0cu << 24);
-            const uint32_t x01 = __builtin_amdgcn_perm(w[1][wd], w[0][wd], sel);
-            const uint32_t x23 = __builtin_amdgcn_perm(w[3][wd], w[2][wd], sel);
-            *reinterpret_cast<u32x2 *>(&sm.gs[16 * cg + q][jq]) = u32x2{ (uint32_t)__umul24(x01, 0x3C00u), (uint32_t)__umul24(x23, 0x3C00u) };
+            const uint32_t x01 = __builtin_amdgcn_perm(pd.w[1][wd], pd.w[0][wd], sel);
+            const uint32_t x23 = __builtin_amdgcn_perm(pd.w[3][wd], pd.w[2][wd], sel);
+            *reinterpret_cast<u32x2 *>(&sm.gs[16 * cg + q][swap23(jq)]) = u32x2{ (uint32_t)__umul24(x01, 0x3C00u), (uint32_t)__umul24(x23, 0x3C00u) };
         }
     }
 }
 
-// psi products of one staged chunk into the float32 tiles.  Lane (col, h) forms
-// psi for its row i (yi) and local j = jb + 8 h + q, q < 8; MASK keeps only
-// j > rel (rel = i - j0), needed only in the chunk that holds the diagonal.
-template <int NT, int DP, bool MASK>
-__device__ __forceinline__ void chunk_products(const Smem<NT> &sm, const float (&yi)[DP], int rel, f32x16 (&acc)[NT])
+// psi products of one staged chunk into the float32 tiles, 32 j per step.
+// The distances come from the matrix cores too: D = X_j X_i^T over the KA
+// vector components (v_mfma_f32_32x32x2_f32, NS steps) gives lane (col, h)
+// |y_i - y_j|^2 - 14 for its row i and the 16 j = 8 (r / 4) + 4 h + r % 4,
+// r < 16.  Then psi * 2^14 = 2^-(that), split into float16 hi and lo.
+// Taken in pairs of r, the values for r < 8 are the lane's 8 consecutive k of
+// the first 32 x 16 psi tile and r >= 8 those of the second; k = 8 h + (r % 8)
+// stands for local j = 8 (r % 8 / 4) + 4 h + r % 4 (+16 for the second tile),
+// which is k with bits 2 and 3 swapped, the order in which the columns are
+// staged.  MASK keeps only j > rel (rel = i - j0), needed only in the chunk
+// that holds the diagonal.
+template <int NT, int NS, bool MASK>
+__device__ __forceinline__ void chunk_products(const Smem<NT> &sm, const float (&xi)[NS], int rel, f32x16 (&acc)[NT])
 {
     const int lane = threadIdx.x & 63;
     const int h = lane >> 5;
     const int col = lane & 31;
-#pragma unroll 2
-    for (int jb = 0; jb < JC; jb += KS) {
-        const int jl = jb + 8 * h;
-        float ps[8];
+#pragma unroll 1
+    for (int jb = 0; jb < JC; jb += 2 * KS) {
+        f32x16 dd = f32x16{};
 #pragma unroll
-        for (int q = 0; q < 8; ++q) ps[q] = 0.0f;
+        for (int s = 0; s < NS; ++s)
+            dd = __builtin_amdgcn_mfma_f32_32x32x2f32(sm.xs[2 * s + h][jb + col], xi[s], dd, 0, 0, 0);
+        u32x4 ah[2], al[2];
 #pragma unroll
-        for (int d = 0; d < DP; ++d) {
-            const f32x4 ya = *reinterpret_cast<const f32x4 *>(&sm.ys[d][jl]);
-            const f32x4 yb = *reinterpret_cast<const f32x4 *>(&sm.ys[d][jl + 4]);
-            const float yj[8] = { ya.x, ya.y, ya.z, ya.w, yb.x, yb.y, yb.z, yb.w };
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const float df = yi[d] - yj[q];
-                ps[q] = fmaf(df, df, ps[q]);
-            }
-        }
-        u32x4 ah, al;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            float a = __builtin_amdgcn_exp2f(-ps[2 * k]) * PSI_SCALE;
-            float b = __builtin_amdgcn_exp2f(-ps[2 * k + 1]) * PSI_SCALE;
+        for (int k = 0; k < 8; ++k) {
+            const int r = 2 * k;
+            float a = __builtin_amdgcn_exp2f(-dd[r]);
+            float b = __builtin_amdgcn_exp2f(-dd[r + 1]);
             if (MASK) {
-                a = (jl + 2 * k > rel) ? a : 0.0f;
-                b = (jl + 2 * k + 1 > rel) ? b : 0.0f;
+                const int ja = jb + 8 * (r >> 2) + 4 * h + (r & 3);
+                a = (ja > rel) ? a : 0.0f;
+                b = (ja + 1 > rel) ? b : 0.0f;
             }
             const uint32_t hw = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(a, b));
             // residuals a - hi_a, b - hi_b, each one mixed-precision multiply-add
@@ -169,16 +258,20 @@ __device__ __forceinline__ void chunk_products(const Smem<NT> &sm, const float (
             float ra, rb;
             asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(ra) : "v"(hw), "v"(a));
             asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(rb) : "v"(hw), "v"(b));
-            ah[k] = hw;
-            al[k] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(ra, rb));
+            ah[k >> 2][k & 3] = hw;
+            al[k >> 2][k & 3] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(ra, rb));
         }
-        const f16x8 A_hi = __builtin_bit_cast(f16x8, ah);
-        const f16x8 A_lo = __builtin_bit_cast(f16x8, al);
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const f16x8 B = *reinterpret_cast<const f16x8 *>(&sm.gs[32 * t + col][jl]);
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A_hi, B, acc[t], 0, 0, 0);
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A_lo, B, acc[t], 0, 0, 0);
+        for (int m = 0; m < 2; ++m) {
+            const f16x8 A_hi = __builtin_bit_cast(f16x8, ah[m]);
+            const f16x8 A_lo = __builtin_bit_cast(f16x8, al[m]);
+            const int jl = jb + KS * m + 8 * h;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const f16x8 B = *reinterpret_cast<const f16x8 *>(&sm.gs[32 * t + col][jl]);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A_hi, B, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A_lo, B, acc[t], 0, 0, 0);
+            }
         }
     }
 }
@@ -237,8 +330,8 @@ __device__ __forceinline__ void flush(const EParams &p, Smem<NT> &sm, f32x16 (&a
 // equal contiguous pieces, so the launch has enough equal-sized workgroups to
 // keep every compute unit busy to the end.
 // RR: row-weight columns the reduction carries (1 covers R <= 1, 3 covers R <= 3).
-template <int NT, int DP, int RR>
-__global__ __launch_bounds__(256) void tp_pairsum_kernel(const EParams p, const int K)
+template <int NT, int NS, int RR>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void tp_pairsum_kernel(const EParams p, const int K)
 {
     constexpr int C = 32 * NT;
     __shared__ __align__(16) Smem<NT> sm;
@@ -265,22 +358,29 @@ __global__ __launch_bounds__(256) void tp_pairsum_kernel(const EParams p, const 
     const int64_t L2 = b2 > b1 ? (p.n - b2 * ROWS + JC - 1) / JC : 0;
     const int64_t L = L1 + L2;
     const int64_t v0 = k * L / K, v1 = (k + 1) * L / K;
-    float yi[DP];
+    float c[MAXD];
+    centre<NT>(p, sm, c);
+    float xi[NS];
     int64_t cur = -1;
     int since = 0;
+    // chunk v: row block b1 for v < L1 (chunk v of its row), else b2 (chunk v - L1)
+    auto chunk_j0 = [&](int64_t v) { return v < L1 ? b1 * ROWS + v * JC : b2 * ROWS + (v - L1) * JC; };
+    Pending<2 * NS> pd;
+    if (v0 < v1) load_chunk<NT, 2 * NS>(p, chunk_j0(v0), pd);
     for (int64_t v = v0; v < v1; ++v) {
         const int64_t blk = v < L1 ? b1 : b2;
         const int64_t c0 = v < L1 ? v : v - L1;      // chunk within the block's row
-        const int64_t j0 = blk * ROWS + c0 * JC;
+        const int64_t j0 = chunk_j0(v);
         if (blk != cur) {
-            setup_rows<NT, DP>(p, sm, blk * ROWS, yi);
+            setup_rows<NT, NS>(p, sm, blk * ROWS, c, xi);
             cur = blk;
         }
         __syncthreads();
-        stage_chunk<NT, DP>(p, sm, j0);
+        store_chunk<NT, 2 * NS>(p, sm, j0, pd, c);
         __syncthreads();
-        if (c0 == 0) chunk_products<NT, DP, true>(sm, yi, wave * 32 + col, acc);
-        else chunk_products<NT, DP, false>(sm, yi, 0, acc);
+        if (v + 1 < v1) load_chunk<NT, 2 * NS>(p, chunk_j0(v + 1), pd);
+        if (c0 == 0) chunk_products<NT, NS, true>(sm, xi, wave * 32 + col, acc);
+        else chunk_products<NT, NS, false>(sm, xi, 0, acc);
         const bool block_ends = v + 1 == v1 || v + 1 == L1;
         if (++since == FL || block_ends) {
             flush<NT, RR>(p, sm, acc, part);
@@ -305,7 +405,7 @@ __global__ __launch_bounds__(256) void tp_pairsum_kernel(const EParams p, const 
         }
 }
 
-template <int NT, int DP, int RR>
+template <int NT, int NS, int RR>
 void launch_ntd(const EParams &p, hipStream_t st)
 {
     const int64_t nb = (p.n + ROWS - 1) / ROWS;
@@ -317,18 +417,17 @@ void launch_ntd(const EParams &p, hipStream_t st)
     int64_t K = (16384 + pairs - 1) / pairs;
     K = K > chunks / 2 ? chunks / 2 : K;
     K = K < 1 ? 1 : K;
-    hipLaunchKernelGGL((tp_pairsum_kernel<NT, DP, RR>), dim3((unsigned)(pairs * K)), dim3(256), 0, st, p, (int)K);
+    hipLaunchKernelGGL((tp_pairsum_kernel<NT, NS, RR>), dim3((unsigned)(pairs * K)), dim3(256), 0, st, p, (int)K);
 }
 
 template <int NT, int RR>
 void launch_ntr(const EParams &p, hipStream_t st)
 {
-    switch (p.D) {   // coordinates per event, padded up to the next instantiated count
+    switch (p.D) {   // distance-vector components D + 2, in pairs
     case 1: case 2: launch_ntd<NT, 2, RR>(p, st); break;
-    case 3: case 4: launch_ntd<NT, 4, RR>(p, st); break;
-    case 5: launch_ntd<NT, 5, RR>(p, st); break;
-    case 6: launch_ntd<NT, 6, RR>(p, st); break;
-    default: launch_ntd<NT, 8, RR>(p, st); break;
+    case 3: case 4: launch_ntd<NT, 3, RR>(p, st); break;
+    case 5: case 6: launch_ntd<NT, 4, RR>(p, st); break;
+    default: launch_ntd<NT, 5, RR>(p, st); break;
     }
 }
 

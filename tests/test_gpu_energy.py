@@ -3,7 +3,11 @@
 Tolerance.  The device forms coordinates in float32 (relative rounding 2^-24 of
 masses ~1-2 GeV) and psi in float32 with the hardware exp2 (a few ulp): the
 distance error d * |delta d| / sigma^2 with |delta d| <~ 4e-7 GeV puts each psi
-within ~1e-6 (relative) of the float64 value at sigma = 0.3 GeV.  The matrix
+within ~1e-6 (relative) of the float64 value at sigma = 0.3 GeV.  The squared
+distance itself is a float32 dot product of centred vectors on the matrix
+cores (rounding ~10 * 2^-24 * (2 |v_i|^2 + 2 |v_j|^2 + 14) with |v|^2 < 3 here:
+in a float32 emulation on these coordinates, psi within 1.7e-6, rms 3e-7, of
+random sign).  The matrix
 cores take psi as two float16 terms whose sum is within 2^-20 (~1e-6) of it,
 and accumulate exact products in float32 tiles that are reduced into float64
 every 1024 j: 128 accumulation roundings of 2^-24 (worst case ~8e-6, typically
