@@ -109,7 +109,6 @@ def cpu_baseline(samples, budget_events, want_counts_of):
 # operation per lane per cycle (packed float32 is not used)
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 MFMA_F16_PEAK_TFLOPS = 2500.0   # dense float16 matrix-core peak
-MFMA_F32_PEAK_TFLOPS = 157.3    # dense float32 matrix-core peak
 
 
 def energy_leg(n, nperm, dev, per_pass=126, cpu_events=0):
@@ -163,11 +162,11 @@ def energy_leg(n, nperm, dev, per_pass=126, cpu_events=0):
     T_obs = T_obs_passes[0]
     T_perm = np.array(T_perm)
     # psi is symmetric: the kernel forms each unordered pair once per launch.  Per
-    # pair and launch it spends three units, which on gfx950 do not overlap
-    # (measured), so its bound is the sum of the three minimum times:
-    #   distances: x_i . x_j over KA = 2 ceil((D + 2) / 2) components on the
-    #     float32 matrix cores, 2 KA flops;
-    #   contraction with the C columns: two float16 terms, 4 C flops;
+    # pair and launch it spends two units, which on gfx950 do not overlap
+    # (measured), so its bound is the sum of their minimum times:
+    #   float16 matrix cores: the distances x_i . x_j as one contraction over
+    #     32 float16 slots (split terms), 64 flops; the contraction with the C
+    #     columns as two float16 terms, 4 C flops;
     #   vector ALU: exp2, the float16 split (half a pack, one residual, half a
     #     pack): 3 lane operations (exp2 counted as one issue slot, which if
     #     anything overstates the peak).
@@ -176,14 +175,12 @@ def energy_leg(n, nperm, dev, per_pass=126, cpu_events=0):
     # beside it for comparison with an all-vector-ALU design.
     pairs = n * (n - 1) / 2.0
     D = len(masks)
-    KA = 2 * ((D + 3) // 2)
     npairs = pairs * len(ks)
     ops = (2 * D + 1) * npairs
     mfma_flops = sum(4.0 * c.shape[1] * pairs for c in colsets)
-    f32_flops = 2.0 * KA * npairs
+    dist_flops = 64.0 * npairs
     valu_ops = 3.0 * npairs
-    t_bound = (f32_flops / (MFMA_F32_PEAK_TFLOPS * 1e12) + mfma_flops / (MFMA_F16_PEAK_TFLOPS * 1e12)
-               + valu_ops / (VALU_PEAK_TOPS * 1e12))
+    t_bound = (dist_flops + mfma_flops) / (MFMA_F16_PEAK_TFLOPS * 1e12) + valu_ops / (VALU_PEAK_TOPS * 1e12)
     C0 = colsets[0].shape[1]
     log(f"energy test: {n} events, {nperm} permutations in {len(ks)} launches of {C0} columns, "
         f"{sec * 1e3:.1f} ms, {sec * 1e3 / nperm:.2f} ms per permutation, T = {T_obs:.4e}")
@@ -211,13 +208,13 @@ def energy_leg(n, nperm, dev, per_pass=126, cpu_events=0):
             "unordered_pairs_per_s": pairs * len(ks) / sec,
             "roofline": {"bound": "mfma+alu", "achieved": npairs / sec / 1e12, "peak": npairs / t_bound / 1e12,
                          "unit": "Tpair/s", "frac": t_bound / sec,
-                         "per_pair": {"mfma_f32_flops": 2 * KA, "mfma_f16_flops": 4 * C0, "valu_lane_ops": 3},
-                         "mfma_f32_frac": f32_flops / sec / 1e12 / MFMA_F32_PEAK_TFLOPS,
-                         "mfma_f16_frac": mfma_flops / sec / 1e12 / MFMA_F16_PEAK_TFLOPS,
+                         "per_pair": {"mfma_f16_flops_distance": 64, "mfma_f16_flops_columns": 4 * C0,
+                                      "valu_lane_ops": 3},
+                         "mfma_f16_frac": (dist_flops + mfma_flops) / sec / 1e12 / MFMA_F16_PEAK_TFLOPS,
                          "valu_frac": valu_ops / sec / 1e12 / VALU_PEAK_TOPS,
                          "method_alu_tops": ops / sec / 1e12, "method_alu_frac": ops / sec / 1e12 / VALU_PEAK_TOPS,
                          "method_lane_ops_per_pair": 2 * D + 1,
-                         "dtype": "f32 (distances, psi), f16 x2 (products), f32 (tiles), f64 (sums)"},
+                         "dtype": "f16 x2 (distances, products), f32 (psi, tiles), f64 (sums)"},
             "T_obs": T_obs, "T_obs_spread_over_launches": max(T_obs_passes) - min(T_obs_passes),
             "p_value": float(np.count_nonzero(T_perm > T_obs)) / nperm,
             "paper_context": "one permutation at 1e6 events took ~30 min on NVIDIA M2070 / K40c (Sect. 6)"}

@@ -16,13 +16,17 @@
 //
 // Both steps run on the matrix cores.  Distances: with the scaled coordinates
 // centred on the mean c of the first 256 events, v = y yscale - c, the vectors
-// x_j = (v_j, |v_j|^2, 1) and x_i = (-2 v_i, 1, |v_i|^2 - 14) give
-// x_i . x_j = |v_i - v_j|^2 - 14, a float32 contraction over D + 2 components
-// (v_mfma_f32_32x32x2_f32), so psi * 2^14 = 2^-(x_i . x_j) costs one exp2 per
-// pair on the vector ALU.  Rounding of that dot product is bounded by about
-// (D + 10) 2^-24 (2 |v_i|^2 + 2 |v_j|^2 + 14); centring keeps the |v|^2 small
-// (a few units for invariant masses at sigma ~ 0.3 GeV), which puts psi within
-// ~2e-6 (relative, random sign) of the value for the same float32 coordinates.
+// x_j = (v_j, |v_j|^2, 1) and x_i = (-2 v_i, 1, |v_i|^2) give
+// x_i . x_j = |v_i - v_j|^2.  Each vector is split into two float16 terms
+// (hi, lo: 2^-22 relative) and laid out so that one float16 contraction over
+// 32 slots forms hi.hi + hi.lo + lo.hi - 14 (the -14, the psi scale, is an
+// exact extra slot): two v_mfma_f32_32x32x16_f16 per 32 x 32 pairs, with exact
+// products and float32 accumulation.  Then psi * 2^14 = 2^-(that) costs one
+// exp2 per pair on the vector ALU.  The rounding of the squared distance is
+// about 2^-22 (2 |v_i|^2 + 2 |v_j|^2) plus the float32 accumulation; centring
+// keeps |v|^2 small (a few units for invariant masses at sigma ~ 0.3 GeV, ~100
+// at 0.05 GeV), and the errors are of random sign, so sums over many pairs
+// keep ~1e-8.  Events with |v|^2 > VMAX2 make the sums NaN.
 // V = Psi G is then a dense contraction over j in half precision with float32
 // accumulation (v_mfma_f32_32x32x16_f16): psi * 2^14 is split into two float16
 // terms hi = rtz(psi), lo = rtz(psi - hi): the difference is exact in float32
@@ -59,13 +63,18 @@ constexpr int JC = 128;       // j per LDS chunk
 constexpr int KS = 16;        // j per matrix-core step
 constexpr int FL = 8;         // chunks per float32 -> float64 reduction
 constexpr int GPAD = 8;       // float16 padding per staged column (spreads LDS banks)
+constexpr int XS = 40;        // float16 slots per staged j vector: 32 used, 8 padding (spreads LDS banks)
 constexpr float PSI_LOG2 = 14.0f;             // psi is formed scaled by 2^14
+// Largest |v|^2 (squared scaled distance from the centre) of an event: the
+// distance rounding grows as 2^-22 |v|^2, and float16 holds |v|^2 only below
+// 65504.  An event beyond it gets a NaN norm, which makes every sum NaN.
+constexpr float VMAX2 = 1024.0f;
 constexpr double PSI_UNSCALE = 1.0 / 16384.0;
 
 template <int NT>
 struct Smem {
     static constexpr int C = 32 * NT;
-    float xs[MAXD + 2][JC];             // chunk j vectors, [k][j]: y_j - c (D), |y_j - c|^2, 1, zeros
+    uint16_t xh[JC][XS];                // chunk j operand vectors, float16 (see split_slots)
     float cw[4][MAXD];                  // per-wave coordinate sums for the centre c
     uint16_t gs[C][JC + GPAD];          // columns of the chunk, [c][j], float16 0 or 1
     uint8_t gi[ROWS * C];               // columns of this block's rows, [i][c]
@@ -92,15 +101,47 @@ __device__ __forceinline__ void centre(const EParams &p, Smem<NT> &sm, float (&c
     for (int d = 0; d < MAXD; ++d) c[d] = ((sm.cw[0][d] + sm.cw[1][d]) + (sm.cw[2][d] + sm.cw[3][d])) / (float)(m > 0 ? m : 1);
 }
 
+// Distance operands in float16.  A float32 vector x of KA <= 10 components is
+// split into hi = f16(x) and lo = f16(x - hi) (the difference exact in
+// float32, hi + lo within 2^-22 |x|); a row vector takes the 32 slots
+// [hi | lo | hi | -14 | 0] and a column vector [hi | hi | lo | 1 | 0], so that
+// their float16 dot product over the 32 slots, with exact products and float32
+// accumulation, is hi.hi + lo.hi + hi.lo - 14: x_i . x_j - 14 up to the lo.lo
+// term (2^-22 relative).
+// Slot s of the row (COL = false) or column (COL = true) pattern:
+template <int KA, bool COL>
+__device__ __forceinline__ uint16_t slot(const uint16_t (&hi)[KA], const uint16_t (&lo)[KA], int s)
+{
+    if (s < KA) return hi[s];
+    if (s < 2 * KA) return COL ? hi[s - KA] : lo[s - KA];
+    if (s < 3 * KA) return COL ? lo[s - 2 * KA] : hi[s - 2 * KA];
+    // the scale of psi, exact in float16: 1 x (-14) in the first free slot
+    if (s == 3 * KA) return __builtin_bit_cast(uint16_t, COL ? (_Float16)1.0f : (_Float16)(-PSI_LOG2));
+    return 0;
+}
+
+template <int KA>
+__device__ __forceinline__ void split16(const float (&x)[KA], uint16_t (&hi)[KA], uint16_t (&lo)[KA])
+{
+#pragma unroll
+    for (int k = 0; k < KA; ++k) {
+        const _Float16 a = (_Float16)x[k];
+        const _Float16 b = (_Float16)(x[k] - (float)a);
+        hi[k] = __builtin_bit_cast(uint16_t, a);
+        lo[k] = __builtin_bit_cast(uint16_t, b);
+    }
+}
+
 // Row block setup: columns and row weights of rows ib .. ib + ROWS - 1, and
-// this lane's entries of its row's vector x_i = (-2 (y_i - c), 1,
-// |y_i - c|^2 - 14) (scaled coordinates, so psi = 2^-(scaled distance)^2):
-// x_i . x_j = |y_i - y_j|^2 - 14 for the chunk vectors x_j.  Lane half h
-// holds components 2 s + h, s < NS.
+// this lane's operand halves of its row's vector x_i = (-2 (y_i - c), 1,
+// |y_i - c|^2) (scaled coordinates, so psi = 2^-(scaled distance)^2):
+// x_i . x_j = |y_i - y_j|^2 for the chunk vectors x_j.  Lane half h holds
+// slots 16 m + 8 h .. + 7 of the row pattern for the two distance steps m.
 template <int NT, int NS>
-__device__ __forceinline__ void setup_rows(const EParams &p, Smem<NT> &sm, int64_t ib, const float (&c)[MAXD], float (&xi)[NS])
+__device__ __forceinline__ void setup_rows(const EParams &p, Smem<NT> &sm, int64_t ib, const float (&c)[MAXD], u32x4 (&xi)[2])
 {
     constexpr int C = 32 * NT;
+    constexpr int KA = 2 * NS;
     const int tid = threadIdx.x;
     const int h = (tid >> 5) & 1;
     const int64_t i = ib + (tid >> 6) * 32 + (tid & 31);
@@ -119,23 +160,31 @@ __device__ __forceinline__ void setup_rows(const EParams &p, Smem<NT> &sm, int64
 #pragma unroll
         for (int q = 3; q < 8; ++q) sm.rw[tid][q] = 0.0f;
     }
-    float x[2 * NS];
+    float x[KA];
     float nrm = 0.0f;
 #pragma unroll
-    for (int k = 0; k < 2 * NS; ++k) x[k] = 0.0f;
+    for (int k = 0; k < KA; ++k) x[k] = 0.0f;
 #pragma unroll
-    for (int d = 0; d < 2 * NS - 2; ++d) {
+    for (int d = 0; d < KA - 2; ++d) {
         const float v = (d < p.D && i < p.n) ? p.Y[d * p.ldY + i] * p.yscale - c[d] : 0.0f;
         nrm = fmaf(v, v, nrm);
         if (d < p.D) x[d] = -2.0f * v;
     }
+    if (!(nrm <= VMAX2)) nrm = __builtin_nanf("");
 #pragma unroll
-    for (int k = 0; k < 2 * NS; ++k) {
+    for (int k = 0; k < KA; ++k) {
         if (k == p.D) x[k] = 1.0f;
-        if (k == p.D + 1) x[k] = nrm - PSI_LOG2;
+        if (k == p.D + 1) x[k] = nrm;
     }
+    uint16_t hi[KA], lo[KA];
+    split16<KA>(x, hi, lo);
 #pragma unroll
-    for (int s = 0; s < NS; ++s) xi[s] = h ? x[2 * s + 1] : x[2 * s];
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int s0 = 16 * m + 8 * h + 2 * w;
+            xi[m][w] = (uint32_t)slot<KA, false>(hi, lo, s0) | ((uint32_t)slot<KA, false>(hi, lo, s0 + 1) << 16);
+        }
 }
 
 // Position of local j in a staged column: bits 2 and 3 swapped, the order in
@@ -188,18 +237,33 @@ __device__ __forceinline__ void store_chunk(const EParams &p, Smem<NT> &sm, int6
     const int tid = threadIdx.x;
     if (tid < JC) {
         const bool real = j0 + tid < p.n;   // padding events sit at the centre
+        float x[KA];
         float nrm = 0.0f;
+#pragma unroll
+        for (int k = 0; k < KA; ++k) x[k] = 0.0f;
 #pragma unroll
         for (int d = 0; d < KA - 2; ++d) {
             const float v = (d < p.D && real) ? pd.y[d] * p.yscale - c[d] : 0.0f;
             nrm = fmaf(v, v, nrm);
-            if (d < p.D) sm.xs[d][tid] = v;
+            if (d < p.D) x[d] = v;
         }
+        if (!(nrm <= VMAX2)) nrm = __builtin_nanf("");
 #pragma unroll
         for (int k = 0; k < KA; ++k) {
-            if (k == p.D) sm.xs[k][tid] = nrm;
-            else if (k == p.D + 1) sm.xs[k][tid] = 1.0f;
-            else if (k > p.D + 1) sm.xs[k][tid] = 0.0f;
+            if (k == p.D) x[k] = nrm;
+            if (k == p.D + 1) x[k] = 1.0f;
+        }
+        uint16_t hi[KA], lo[KA];
+        split16<KA>(x, hi, lo);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            u32x4 w;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int s0 = 8 * q + 2 * e;
+                w[e] = (uint32_t)slot<KA, true>(hi, lo, s0) | ((uint32_t)slot<KA, true>(hi, lo, s0 + 1) << 16);
+            }
+            *reinterpret_cast<u32x4 *>(&sm.xh[tid][8 * q]) = w;
         }
     }
     if (tid < ITEMS) {
@@ -229,8 +293,8 @@ __device__ __forceinline__ void store_chunk(const EParams &p, Smem<NT> &sm, int6
 // which is k with bits 2 and 3 swapped, the order in which the columns are
 // staged.  MASK keeps only j > rel (rel = i - j0), needed only in the chunk
 // that holds the diagonal.
-template <int NT, int NS, bool MASK>
-__device__ __forceinline__ void chunk_products(const Smem<NT> &sm, const float (&xi)[NS], int rel, f32x16 (&acc)[NT])
+template <int NT, bool MASK>
+__device__ __forceinline__ void chunk_products(const Smem<NT> &sm, const u32x4 (&xi)[2], int rel, f32x16 (&acc)[NT])
 {
     const int lane = threadIdx.x & 63;
     const int h = lane >> 5;
@@ -239,8 +303,10 @@ __device__ __forceinline__ void chunk_products(const Smem<NT> &sm, const float (
     for (int jb = 0; jb < JC; jb += 2 * KS) {
         f32x16 dd = f32x16{};
 #pragma unroll
-        for (int s = 0; s < NS; ++s)
-            dd = __builtin_amdgcn_mfma_f32_32x32x2f32(sm.xs[2 * s + h][jb + col], xi[s], dd, 0, 0, 0);
+        for (int m = 0; m < 2; ++m) {
+            const f16x8 A = *reinterpret_cast<const f16x8 *>(&sm.xh[jb + col][16 * m + 8 * h]);
+            dd = __builtin_amdgcn_mfma_f32_32x32x16_f16(A, __builtin_bit_cast(f16x8, xi[m]), dd, 0, 0, 0);
+        }
         u32x4 ah[2], al[2];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -282,7 +348,7 @@ __device__ __forceinline__ void chunk_products(const Smem<NT> &sm, const float (
 // (Psi_upper w_q)_i go through LDS so that every column can take the
 // transposed term sum_i G_ic (Psi_upper w_q)_i.
 template <int NT, int RR>
-__device__ __forceinline__ void flush(const EParams &p, Smem<NT> &sm, f32x16 (&acc)[NT], double (&part)[NT][1 + MAXR])
+__device__ __forceinline__ void flush(const EParams &p, Smem<NT> &sm, f32x16 (&acc)[NT], double (&part)[NT][1 + RR])
 {
     constexpr int C = 32 * NT;
     const int tid = threadIdx.x;
@@ -319,8 +385,10 @@ __device__ __forceinline__ void flush(const EParams &p, Smem<NT> &sm, f32x16 (&a
     for (int t = 0; t < NT; ++t) {
         part[t][0] += 2.0 * (double)s0[t];       // diagonal-type sums are symmetric
         part[t][1] += (double)s1[t];
-        part[t][2] += (double)s2[t];
-        part[t][3] += (double)s3[t];
+        if (RR > 1) {
+            part[t][RR > 1 ? 2 : 1] += (double)s2[t];
+            part[t][RR > 1 ? 3 : 1] += (double)s3[t];
+        }
         acc[t] = f32x16{};
     }
 }
@@ -342,11 +410,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void t
     const int col = lane & 31;
     const int64_t nb = (p.n + ROWS - 1) / ROWS;
     for (int e = tid; e < C * (1 + MAXR); e += 256) (&sm.red[0][0])[e] = 0.0;
-    double part[NT][1 + MAXR];
+    double part[NT][1 + RR];
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int q = 0; q <= MAXR; ++q) part[t][q] = 0.0;
+        for (int q = 0; q <= RR; ++q) part[t][q] = 0.0;
     f32x16 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = f32x16{};
@@ -360,7 +428,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void t
     const int64_t v0 = k * L / K, v1 = (k + 1) * L / K;
     float c[MAXD];
     centre<NT>(p, sm, c);
-    float xi[NS];
+    u32x4 xi[2];
     int64_t cur = -1;
     int since = 0;
     // chunk v: row block b1 for v < L1 (chunk v of its row), else b2 (chunk v - L1)
@@ -379,8 +447,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void t
         store_chunk<NT, 2 * NS>(p, sm, j0, pd, c);
         __syncthreads();
         if (v + 1 < v1) load_chunk<NT, 2 * NS>(p, chunk_j0(v + 1), pd);
-        if (c0 == 0) chunk_products<NT, NS, true>(sm, xi, wave * 32 + col, acc);
-        else chunk_products<NT, NS, false>(sm, xi, 0, acc);
+        if (c0 == 0) chunk_products<NT, true>(sm, xi, wave * 32 + col, acc);
+        else chunk_products<NT, false>(sm, xi, 0, acc);
         const bool block_ends = v + 1 == v1 || v + 1 == L1;
         if (++since == FL || block_ends) {
             flush<NT, RR>(p, sm, acc, part);
@@ -392,7 +460,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void t
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int q = 0; q <= MAXR; ++q) {
+        for (int q = 0; q <= RR; ++q) {
             double x = part[t][q];
             x += __shfl_xor(x, 32);
             if (h == 0 && q <= R) atomicAdd(&sm.red[32 * t + col][q], x);

@@ -258,3 +258,57 @@ def test_raw_pair_sums_all_tile_counts(tp, C, nrow, n):
     for q in range(nrow):
         wq = Gf[:, q] @ V                         # sum_i G_iq (Psi G)_ic
         assert np.all(np.abs(S[:, 1 + q] - wq) <= 1e-5 * wq + 1e-9), q
+
+
+@pytest.mark.parametrize("sigma", [0.05, 0.1, 2.0])
+def test_raw_pair_sums_sigma_range(tp, sigma):
+    """Pair sums against the dense float64 psi matrix for narrow and wide kernels.  The
+    squared distances are a float32 dot product of centred vectors, whose rounding grows
+    with the squared distance of the events from the centre in units of sigma (|v|^2 up to
+    ~100 at sigma = 0.05 GeV here): single psi values lose accuracy (a float32 emulation on
+    these coordinates gives up to ~5e-5 relative at sigma = 0.05), but the errors are of
+    random sign, so the sums stay within the same 1e-5 as at sigma = 0.3."""
+    n, C, nrow = 2051, 64, 2
+    ch, s = sample(n, 911)
+    ds = tp.DeviceSample.from_sample(s)
+    Yg = tp.coords(ds, MASKS, 1e-3)
+    rng = np.random.default_rng(912)
+    G = (rng.uniform(size=(n, C)) < rng.uniform(0.1, 0.9, size=C)).astype(np.uint8)
+    sums = tp.pairsums(Yg, torch.from_numpy(G).cuda(), sigma, nrow=nrow)
+    torch.cuda.synchronize()
+    S = sums.cpu().numpy()
+    comps, _ = s.numpy()
+    Yo = energy.invariant_masses(comps, MASKS) * 1e-3
+    Psi = energy.psi_block(Yo, Yo, sigma)
+    np.fill_diagonal(Psi, 0.0)
+    Gf = G.astype(np.float64)
+    V = Psi @ Gf
+    want0 = np.einsum("ic,ic->c", Gf, V)
+    assert np.all(np.abs(S[:, 0] - want0) <= 1e-5 * want0 + 1e-9)
+    for q in range(nrow):
+        wq = Gf[:, q] @ V
+        assert np.all(np.abs(S[:, 1 + q] - wq) <= 1e-5 * wq + 1e-9), q
+
+
+def test_pair_sums_far_event_gives_nan(tp):
+    """An event whose scaled squared distance from the centre (the mean of the first 256
+    events) exceeds 1024, i.e. ~37 sigma away, is outside the range in which the matrix-core
+    distances are accurate: the sums come out NaN instead of silently imprecise.  The same
+    coordinates without that event give finite sums that match the dense float64 psi."""
+    n, C, sigma = 300, 32, 0.3
+    rng = np.random.default_rng(31)
+    Yh = rng.normal(1.0, 0.3, size=(2, n)).astype(np.float32)
+    G = (rng.uniform(size=(n, C)) < 0.5).astype(np.uint8)
+    Gd = torch.from_numpy(G).cuda()
+    ok = tp.pairsums(torch.from_numpy(Yh).cuda(), Gd, sigma, nrow=1)
+    Yfar = Yh.copy()
+    Yfar[:, n - 1] = 20.0                               # ~ (19 GeV / 0.3 GeV) * 0.85 = 54 scaled units
+    bad = tp.pairsums(torch.from_numpy(Yfar).cuda(), Gd, sigma, nrow=1)
+    torch.cuda.synchronize()
+    assert np.all(np.isnan(bad.cpu().numpy()))
+    S = ok.cpu().numpy()
+    Psi = energy.psi_block(Yh.astype(np.float64), Yh.astype(np.float64), sigma)
+    np.fill_diagonal(Psi, 0.0)
+    Gf = G.astype(np.float64)
+    want0 = np.einsum("ic,ic->c", Gf, Psi @ Gf)
+    assert np.all(np.abs(S[:, 0] - want0) <= 1e-5 * want0 + 1e-9)
