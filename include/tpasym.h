@@ -298,10 +298,12 @@ int tp_coords(const tp_events *ev, const int32_t *masks, int32_t ncoord, double 
  * or 128; its first nrow (0..3) columns are also the row weights); sums
  * [ncols][1 + nrow] float64 (device, accumulated: zero it once).  sigma > 0.
  * psi is formed for pairs j > i only (psi is symmetric): the squared
- * distance as a float32 dot product of (coordinates - centre, squared norm)
- * vectors on the matrix cores (centre: mean of the first 256 events; rounding
- * grows with the squared distance of the events from it), then the hardware
- * exp2.  psi enters the matrix cores again as two float16 terms (truncation
+ * distance as a dot product of (coordinates - centre, squared norm) vectors
+ * split into float16 terms on the matrix cores (centre: mean of the first 256
+ * events; rounding grows with the squared distance of the events from it, in
+ * units of sigma, and is of random sign), then the hardware exp2.  An event
+ * farther than ~37 sigma from the centre (scaled squared distance > 1024)
+ * makes the sums NaN.  psi enters the matrix cores again as two float16 terms (truncation
  * of psi * 2^14 and of the remainder: together within 2^-20 of psi,
  * relative); the 0/1 columns are exact in float16, products are accumulated
  * in float32 over 1024 j and then in float64.  Sums are accurate to ~1e-5

@@ -74,7 +74,7 @@ constexpr double PSI_UNSCALE = 1.0 / 16384.0;
 template <int NT>
 struct Smem {
     static constexpr int C = 32 * NT;
-    uint16_t xh[JC][XS];                // chunk j operand vectors, float16 (see split_slots)
+    uint16_t xh[JC][XS];                // chunk j distance operands, float16 slots (see slot())
     float cw[4][MAXD];                  // per-wave coordinate sums for the centre c
     uint16_t gs[C][JC + GPAD];          // columns of the chunk, [c][j], float16 0 or 1
     uint8_t gi[ROWS * C];               // columns of this block's rows, [i][c]
@@ -283,8 +283,8 @@ __device__ __forceinline__ void store_chunk(const EParams &p, Smem<NT> &sm, int6
 }
 
 // psi products of one staged chunk into the float32 tiles, 32 j per step.
-// The distances come from the matrix cores too: D = X_j X_i^T over the KA
-// vector components (v_mfma_f32_32x32x2_f32, NS steps) gives lane (col, h)
+// The distances come from the matrix cores too: the 32 float16 slots of the
+// column and row vectors (two v_mfma_f32_32x32x16_f16) give lane (col, h)
 // |y_i - y_j|^2 - 14 for its row i and the 16 j = 8 (r / 4) + 4 h + r % 4,
 // r < 16.  Then psi * 2^14 = 2^-(that), split into float16 hi and lo.
 // Taken in pairs of r, the values for r < 8 are the lane's 8 consecutive k of

@@ -4,10 +4,10 @@ Tolerance.  The device forms coordinates in float32 (relative rounding 2^-24 of
 masses ~1-2 GeV) and psi in float32 with the hardware exp2 (a few ulp): the
 distance error d * |delta d| / sigma^2 with |delta d| <~ 4e-7 GeV puts each psi
 within ~1e-6 (relative) of the float64 value at sigma = 0.3 GeV.  The squared
-distance itself is a float32 dot product of centred vectors on the matrix
-cores (rounding ~10 * 2^-24 * (2 |v_i|^2 + 2 |v_j|^2 + 14) with |v|^2 < 3 here:
-in a float32 emulation on these coordinates, psi within 1.7e-6, rms 3e-7, of
-random sign).  The matrix
+distance itself is a dot product of centred vectors split into float16 terms on
+the matrix cores (rounding ~2^-22 * (2 |v_i|^2 + 2 |v_j|^2) with |v|^2 < 3 here:
+in an emulation on these coordinates, psi within 2e-6, rms 3e-7, of random
+sign).  The matrix
 cores take psi as two float16 terms whose sum is within 2^-20 (~1e-6) of it,
 and accumulate exact products in float32 tiles that are reduced into float64
 every 1024 j: 128 accumulation roundings of 2^-24 (worst case ~8e-6, typically
@@ -263,10 +263,10 @@ def test_raw_pair_sums_all_tile_counts(tp, C, nrow, n):
 @pytest.mark.parametrize("sigma", [0.05, 0.1, 2.0])
 def test_raw_pair_sums_sigma_range(tp, sigma):
     """Pair sums against the dense float64 psi matrix for narrow and wide kernels.  The
-    squared distances are a float32 dot product of centred vectors, whose rounding grows
+    squared distances are a float16-split dot product of centred vectors, whose rounding grows
     with the squared distance of the events from the centre in units of sigma (|v|^2 up to
-    ~100 at sigma = 0.05 GeV here): single psi values lose accuracy (a float32 emulation on
-    these coordinates gives up to ~5e-5 relative at sigma = 0.05), but the errors are of
+    ~100 at sigma = 0.05 GeV here): single psi values lose accuracy (an emulation on these
+    coordinates gives up to ~7e-5 relative at sigma = 0.05), but the errors are of
     random sign, so the sums stay within the same 1e-5 as at sigma = 0.3."""
     n, C, nrow = 2051, 64, 2
     ch, s = sample(n, 911)
