@@ -76,6 +76,7 @@ struct Smem {
     static constexpr int C = 32 * NT;
     uint16_t xh[JC][XS];                // chunk j distance operands, float16 slots (see slot())
     float cw[4][MAXD];                  // per-wave coordinate sums for the centre c
+    float cen[MAXD];                    // the centre c
     uint16_t gs[C][JC + GPAD];          // columns of the chunk, [c][j], float16 0 or 1
     uint8_t gi[ROWS * C];               // columns of this block's rows, [i][c]
     float rw[ROWS][8];                  // per row: weights G[i][q] (0..2), (Psi_upper G)[i][q] (4..6)
@@ -85,7 +86,7 @@ struct Smem {
 // Centre c of the scaled coordinates: the mean of the first min(n, 256)
 // events, formed in a fixed order so that every workgroup gets the same bits.
 template <int NT>
-__device__ __forceinline__ void centre(const EParams &p, Smem<NT> &sm, float (&c)[MAXD])
+__device__ __forceinline__ void centre(const EParams &p, Smem<NT> &sm)
 {
     const int tid = threadIdx.x;
     const int64_t m = p.n < 256 ? p.n : 256;
@@ -97,8 +98,9 @@ __device__ __forceinline__ void centre(const EParams &p, Smem<NT> &sm, float (&c
         if ((tid & 63) == 0) sm.cw[tid >> 6][d] = x;
     }
     __syncthreads();
-#pragma unroll
-    for (int d = 0; d < MAXD; ++d) c[d] = ((sm.cw[0][d] + sm.cw[1][d]) + (sm.cw[2][d] + sm.cw[3][d])) / (float)(m > 0 ? m : 1);
+    if (tid < MAXD)
+        sm.cen[tid] = ((sm.cw[0][tid] + sm.cw[1][tid]) + (sm.cw[2][tid] + sm.cw[3][tid])) / (float)(m > 0 ? m : 1);
+    __syncthreads();
 }
 
 // Distance operands in float16.  A float32 vector x of KA <= 10 components is
@@ -138,7 +140,7 @@ __device__ __forceinline__ void split16(const float (&x)[KA], uint16_t (&hi)[KA]
 // x_i . x_j = |y_i - y_j|^2 for the chunk vectors x_j.  Lane half h holds
 // slots 16 m + 8 h .. + 7 of the row pattern for the two distance steps m.
 template <int NT, int NS>
-__device__ __forceinline__ void setup_rows(const EParams &p, Smem<NT> &sm, int64_t ib, const float (&c)[MAXD], u32x4 (&xi)[2])
+__device__ __forceinline__ void setup_rows(const EParams &p, Smem<NT> &sm, int64_t ib, u32x4 (&xi)[2])
 {
     constexpr int C = 32 * NT;
     constexpr int KA = 2 * NS;
@@ -166,7 +168,7 @@ __device__ __forceinline__ void setup_rows(const EParams &p, Smem<NT> &sm, int64
     for (int k = 0; k < KA; ++k) x[k] = 0.0f;
 #pragma unroll
     for (int d = 0; d < KA - 2; ++d) {
-        const float v = (d < p.D && i < p.n) ? p.Y[d * p.ldY + i] * p.yscale - c[d] : 0.0f;
+        const float v = (d < p.D && i < p.n) ? p.Y[d * p.ldY + i] * p.yscale - sm.cen[d] : 0.0f;
         nrm = fmaf(v, v, nrm);
         if (d < p.D) x[d] = -2.0f * v;
     }
@@ -229,8 +231,7 @@ __device__ __forceinline__ void load_chunk(const EParams &p, int64_t j0, Pending
 }
 
 template <int NT, int KA>
-__device__ __forceinline__ void store_chunk(const EParams &p, Smem<NT> &sm, int64_t j0, const Pending<KA> &pd,
-                                            const float (&c)[MAXD])
+__device__ __forceinline__ void store_chunk(const EParams &p, Smem<NT> &sm, int64_t j0, const Pending<KA> &pd)
 {
     constexpr int C = 32 * NT;
     constexpr int ITEMS = (JC / 4) * (C / 16);
@@ -243,7 +244,7 @@ __device__ __forceinline__ void store_chunk(const EParams &p, Smem<NT> &sm, int6
         for (int k = 0; k < KA; ++k) x[k] = 0.0f;
 #pragma unroll
         for (int d = 0; d < KA - 2; ++d) {
-            const float v = (d < p.D && real) ? pd.y[d] * p.yscale - c[d] : 0.0f;
+            const float v = (d < p.D && real) ? pd.y[d] * p.yscale - sm.cen[d] : 0.0f;
             nrm = fmaf(v, v, nrm);
             if (d < p.D) x[d] = v;
         }
@@ -375,20 +376,16 @@ __device__ __forceinline__ void flush(const EParams &p, Smem<NT> &sm, f32x16 (&a
             const float g = (float)sm.gi[row * C + 32 * t + col];
             s0[t] = fmaf(g, v, s0[t]);
             s1[t] = fmaf(wq.x, v, fmaf(g, vq.x, s1[t]));
-            if (RR > 1) {
-                s2[t] = fmaf(wq.y, v, fmaf(g, vq.y, s2[t]));
-                s3[t] = fmaf(wq.z, v, fmaf(g, vq.z, s3[t]));
-            }
+            if (RR > 1) s2[t] = fmaf(wq.y, v, fmaf(g, vq.y, s2[t]));
+            if (RR > 2) s3[t] = fmaf(wq.z, v, fmaf(g, vq.z, s3[t]));
         }
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         part[t][0] += 2.0 * (double)s0[t];       // diagonal-type sums are symmetric
         part[t][1] += (double)s1[t];
-        if (RR > 1) {
-            part[t][RR > 1 ? 2 : 1] += (double)s2[t];
-            part[t][RR > 1 ? 3 : 1] += (double)s3[t];
-        }
+        if (RR > 1) part[t][RR > 1 ? 2 : 1] += (double)s2[t];
+        if (RR > 2) part[t][RR > 2 ? 3 : 1] += (double)s3[t];
         acc[t] = f32x16{};
     }
 }
@@ -397,7 +394,7 @@ __device__ __forceinline__ void flush(const EParams &p, Smem<NT> &sm, f32x16 (&a
 // row); their chunks, block g's first, form one list that K workgroups share in
 // equal contiguous pieces, so the launch has enough equal-sized workgroups to
 // keep every compute unit busy to the end.
-// RR: row-weight columns the reduction carries (1 covers R <= 1, 3 covers R <= 3).
+// RR: row-weight columns the reduction carries (RR covers R <= RR).
 template <int NT, int NS, int RR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void tp_pairsum_kernel(const EParams p, const int K)
 {
@@ -426,8 +423,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void t
     const int64_t L2 = b2 > b1 ? (p.n - b2 * ROWS + JC - 1) / JC : 0;
     const int64_t L = L1 + L2;
     const int64_t v0 = k * L / K, v1 = (k + 1) * L / K;
-    float c[MAXD];
-    centre<NT>(p, sm, c);
+    centre<NT>(p, sm);
     u32x4 xi[2];
     int64_t cur = -1;
     int since = 0;
@@ -440,11 +436,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void t
         const int64_t c0 = v < L1 ? v : v - L1;      // chunk within the block's row
         const int64_t j0 = chunk_j0(v);
         if (blk != cur) {
-            setup_rows<NT, NS>(p, sm, blk * ROWS, c, xi);
+            setup_rows<NT, NS>(p, sm, blk * ROWS, xi);
             cur = blk;
         }
         __syncthreads();
-        store_chunk<NT, 2 * NS>(p, sm, j0, pd, c);
+        store_chunk<NT, 2 * NS>(p, sm, j0, pd);
         __syncthreads();
         if (v + 1 < v1) load_chunk<NT, 2 * NS>(p, chunk_j0(v + 1), pd);
         if (c0 == 0) chunk_products<NT, true>(sm, xi, wave * 32 + col, acc);
@@ -503,6 +499,7 @@ template <int NT>
 void launch_nt(const EParams &p, hipStream_t st)
 {
     if (p.R <= 1) launch_ntr<NT, 1>(p, st);
+    else if (p.R == 2) launch_ntr<NT, 2>(p, st);
     else launch_ntr<NT, 3>(p, st);
 }
 
