@@ -312,3 +312,35 @@ def test_pair_sums_far_event_gives_nan(tp):
     Gf = G.astype(np.float64)
     want0 = np.einsum("ic,ic->c", Gf, Psi @ Gf)
     assert np.all(np.abs(S[:, 0] - want0) <= 1e-5 * want0 + 1e-9)
+
+
+ALL_MASKS = [0b0011, 0b0101, 0b0110, 0b1001, 0b1010, 0b1100, 0b0111, 0b1011, 0b1101, 0b1110, 0b1111]
+
+
+@pytest.mark.parametrize("D,C,nrow", [(1, 32, 0), (2, 128, 3), (3, 64, 2), (4, 128, 1), (6, 32, 3), (7, 64, 1),
+                                      (8, 128, 2), (8, 32, 1)])
+def test_raw_pair_sums_coordinate_counts(tp, D, C, nrow):
+    """Pair sums against the dense float64 psi matrix for 1 to 8 coordinates per event (the
+    distance operands hold D + 2 components, split into float16 slots, so every coordinate
+    count has its own layout) and each row-weight reduction."""
+    n = 1543
+    ch, s = sample(n, 700 + D)
+    masks = ALL_MASKS[:D]
+    ds = tp.DeviceSample.from_sample(s)
+    Yg = tp.coords(ds, masks, 1e-3)
+    rng = np.random.default_rng(800 + D)
+    G = (rng.uniform(size=(n, C)) < rng.uniform(0.1, 0.9, size=C)).astype(np.uint8)
+    sums = tp.pairsums(Yg, torch.from_numpy(G).cuda(), 0.3, nrow=nrow)
+    torch.cuda.synchronize()
+    S = sums.cpu().numpy()
+    comps, _ = s.numpy()
+    Yo = energy.invariant_masses(comps, masks) * 1e-3
+    Psi = energy.psi_block(Yo, Yo, 0.3)
+    np.fill_diagonal(Psi, 0.0)
+    Gf = G.astype(np.float64)
+    V = Psi @ Gf
+    want0 = np.einsum("ic,ic->c", Gf, V)
+    assert np.all(np.abs(S[:, 0] - want0) <= 1e-5 * want0 + 1e-9)
+    for q in range(nrow):
+        wq = Gf[:, q] @ V
+        assert np.all(np.abs(S[:, 1 + q] - wq) <= 1e-5 * wq + 1e-9), q
