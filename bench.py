@@ -402,13 +402,13 @@ def main():
         t1 = torch.cuda.Event(enable_timing=True)
         f64_items = [(ds, ch, bn, *tpasym.new_counts(bn, dev)) for ds, ch, bn, _, _ in items]
         for ds, ch, bn, c, s in f64_items:
-            tpasym.bin(ds, ch, bn, tpasym.TP_PREC_F64, c, s)
+            tpasym.bin(ds, ch, bn, tpasym.TP_PREC_F64, c, s, check=False)
         torch.cuda.synchronize()
         f64_steps = max(3, args.steps // 4)
         t0.record(stream)
         for _ in range(f64_steps):
             for ds, ch, bn, c, s in f64_items:
-                tpasym.bin(ds, ch, bn, tpasym.TP_PREC_F64, c, s)
+                tpasym.bin(ds, ch, bn, tpasym.TP_PREC_F64, c, s, check=False)
         t1.record(stream)
         torch.cuda.synchronize()
         f64_ms = t0.elapsed_time(t1) / f64_steps

@@ -22,6 +22,7 @@ All sums are plain float64 over explicit pairs (blocked only to bound memory).
 """
 from __future__ import annotations
 
+import os
 from fractions import Fraction
 
 import numpy as np
@@ -119,6 +120,58 @@ def pair_sum(Ya, Yb, sigma, same, block=2048):
                 np.fill_diagonal(p, 0.0)
             tot += float(p.sum())
     return tot
+
+
+def column_pair_sums(Y, G, sigma, block=2048):
+    """M[c][d] = sum over ordered pairs i != j of G[i][c] psi_ij G[j][d] for 0/1 (or
+    any real) columns G [n][C]: each pair sum of eq. (2) / eq. (3) between two event
+    sets is one entry (S(A, B) = M[a][b] for disjoint sets a, b; S(A, A) over
+    ordered pairs = M[a][a]).  psi is formed block by block in float64 and
+    contracted with the columns, so many splits of the same events cost one pass
+    over the pairs."""
+    Y = np.asarray(Y, dtype=np.float64)
+    G = np.asarray(G, dtype=np.float64)
+    n = Y.shape[1]
+
+    def rows(i0):                       # one block of rows against every column block
+        M = np.zeros((G.shape[1], G.shape[1]))
+        for j0 in range(0, n, block):
+            p = psi_block(Y[:, i0:i0 + block], Y[:, j0:j0 + block], sigma)
+            if i0 == j0:
+                np.fill_diagonal(p, 0.0)
+            M += G[i0:i0 + block].T @ (p @ G[j0:j0 + block])
+        return M
+
+    # row blocks on the host's cores (numpy releases the interpreter lock)
+    from concurrent.futures import ThreadPoolExecutor
+    workers = min(16, os.cpu_count() or 1, max(1, (n + block - 1) // block))
+    with ThreadPoolExecutor(workers) as ex:
+        return sum(ex.map(rows, range(0, n, block)))
+
+
+def T_eq2_columns(M, a, b, n, nb):
+    """eq. (2) from column pair sums: sets a (n events) and b (nb events) are
+    columns of ``column_pair_sums``; within-sample sums over pairs i < j are
+    half the ordered-pair sums."""
+    return 0.5 * M[a][a] / (n * (n - 1)) + 0.5 * M[b][b] / (nb * (nb - 1)) - M[a][b] / (n * nb)
+
+
+def T_eq3_columns(M, A, Ab, Bk, Bkb, n, nb, bs, bsb, b, b_bar, terms=False):
+    """eq. (3) from column pair sums: columns A, Ab (main samples, n and nb events),
+    Bk, Bkb (background samples, bs and bsb events) of ``column_pair_sums``.  With
+    ``terms`` the ten coefficient x pair-sum terms are returned as three lists
+    (T = sum(t1) + sum(t2) - sum(t3) after the division by each bracket's
+    normalisation, which is applied to the returned terms)."""
+    w, wb = n - b, nb - b_bar
+    t1 = [M[A][A], -2.0 * b / bs * M[A][Bk], b * (b + 1.0) / (bs * (bs - 1.0)) * M[Bk][Bk]]
+    t2 = [M[Ab][Ab], -2.0 * b_bar / bsb * M[Ab][Bkb], b_bar * (b_bar + 1.0) / (bsb * (bsb - 1.0)) * M[Bkb][Bkb]]
+    t3 = [M[A][Ab], -b_bar / bsb * M[A][Bkb], -b / bs * M[Bk][Ab], b * b_bar / (bs * bsb) * M[Bk][Bkb]]
+    t1 = [t / (2.0 * w * (w - 1.0)) for t in t1]
+    t2 = [t / (2.0 * wb * (wb - 1.0)) for t in t2]
+    t3 = [t / (w * wb) for t in t3]
+    if terms:
+        return t1, t2, t3
+    return sum(t1) + sum(t2) - sum(t3)
 
 
 def T_eq2(Y, label, sigma):

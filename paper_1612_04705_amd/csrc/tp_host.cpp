@@ -19,8 +19,8 @@
 #include "tp_kernel.h"
 
 namespace tpk {
-hipError_t launch_pass(int dtype, int prec, int mode, int epl, int k0, int k1, const KParams &kp, int grid, int block,
-                       size_t lds, hipStream_t st);
+hipError_t launch_pass(int dtype, int prec, int mode, int epl, int k0, int k1, bool ord, const KParams &kp, int grid,
+                       int block, size_t lds, hipStream_t st);
 hipError_t launch_exact(int dtype, int mode, const KParams &kp, int grid, hipStream_t st);
 }  // namespace tpk
 
@@ -45,8 +45,13 @@ int fail(int code, const std::string &msg)
             return fail(TP_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
     } while (0)
 
-constexpr uint32_t XCAP = 1u << 20;     // exact-tier list capacity per launch
-constexpr int EXACT_GRID = 16;
+// The exact-tier list holds one entry per event of a launch (the plan's
+// virtual events, at most 2^31), so it cannot overflow: every event the pass
+// defers is decided by the later tiers.
+constexpr uint64_t XCAP_MIN = 1u << 16;
+constexpr uint64_t XCAP_MAX = 1ull << 31;
+constexpr int EXACT_GRID = 128;
+constexpr size_t MAX_PLANS = 256;        // launch plans kept per device
 constexpr size_t LDS_LIMIT = 64 * 1024;
 
 uint64_t fnv(const void *p, size_t n, uint64_t h = 1469598103934665603ull)
@@ -64,12 +69,21 @@ struct Workspace {
     uint64_t *xlist = nullptr;
     uint32_t *xcount = nullptr;
     uint32_t *xdone = nullptr;
+    uint64_t cap = 0;      // list entries
 };
 
-// Samples of one binning scheme: contiguous in the plan's sample table and in
-// the virtual event space; one pass launch each.
+// List capacity for a launch over ``vtotal`` virtual events.
+uint64_t list_capacity(int64_t vtotal)
+{
+    return std::min<uint64_t>(std::max<uint64_t>((uint64_t)vtotal, XCAP_MIN), XCAP_MAX);
+}
+
+// Samples of one binning scheme (and of one kind as to identical-particle
+// ordering): contiguous in the plan's sample table and in the virtual event
+// space; one pass launch each.
 struct Group {
     int k0 = AX_NONE, k1 = AX_NONE;
+    bool ord = false;
     int sbeg = 0, send = 0;
     int64_t vbeg = 0, vend = 0;
     int hist_stride = 0;
@@ -88,6 +102,13 @@ struct Plan {
     hipStream_t made_on = nullptr;
     KSample *dsamples = nullptr;
     double *dedges = nullptr;
+    // the latest enqueued work that reads the plan (a use on another stream
+    // first waits for it, so this event covers every earlier use)
+    hipEvent_t last_use = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool used = false;
+    std::list<uint64_t>::iterator lru_pos;
+    std::vector<uint64_t> graph_keys;   // graphs captured with this plan's tables
 };
 
 struct GraphEntry {
@@ -128,34 +149,37 @@ Device &device(int id)
     return d;
 }
 
-int get_workspace(Device &d, hipStream_t st, Workspace &out)
+// A deferral workspace of ``cap`` list entries; its counters are cleared on ``st``.
+int new_workspace(uint64_t cap, hipStream_t st, Workspace &w)
 {
-    auto it = d.ws.find(st);
-    if (it != d.ws.end()) {
-        out = it->second;
-        return TP_OK;
-    }
-    Workspace w;
-    const size_t bytes = XCAP * sizeof(uint64_t) + 64;
+    const size_t bytes = cap * sizeof(uint64_t) + 64;
     if (hipMalloc(&w.buf, bytes) != hipSuccess) return fail(TP_ENOMEM, "workspace allocation failed");
+    w.cap = cap;
     w.xlist = static_cast<uint64_t *>(w.buf);
-    w.xcount = reinterpret_cast<uint32_t *>(static_cast<char *>(w.buf) + XCAP * sizeof(uint64_t));
+    w.xcount = reinterpret_cast<uint32_t *>(static_cast<char *>(w.buf) + cap * sizeof(uint64_t));
     w.xdone = w.xcount + 1;
     TP_HIP(hipMemsetAsync(w.xcount, 0, 64, st));
-    d.ws[st] = w;
-    out = w;
     return TP_OK;
 }
 
-int new_workspace(hipStream_t st, Workspace &w)
+// The stream's workspace, grown (after the stream's earlier work) to ``cap`` entries.
+int get_workspace(Device &d, hipStream_t st, uint64_t cap, Workspace &out)
 {
-    const size_t bytes = XCAP * sizeof(uint64_t) + 64;
-    if (hipMalloc(&w.buf, bytes) != hipSuccess) return fail(TP_ENOMEM, "workspace allocation failed");
-    w.xlist = static_cast<uint64_t *>(w.buf);
-    w.xcount = reinterpret_cast<uint32_t *>(static_cast<char *>(w.buf) + XCAP * sizeof(uint64_t));
-    w.xdone = w.xcount + 1;
-    TP_HIP(hipMemsetAsync(w.xcount, 0, 64, st));
-    TP_HIP(hipStreamSynchronize(st));
+    auto it = d.ws.find(st);
+    if (it != d.ws.end() && it->second.cap >= cap) {
+        out = it->second;
+        return TP_OK;
+    }
+    if (it != d.ws.end()) {
+        TP_HIP(hipStreamSynchronize(st));
+        hipFree(it->second.buf);
+        d.ws.erase(it);
+    }
+    Workspace w;
+    const int rc = new_workspace(cap, st, w);
+    if (rc) return rc;
+    d.ws[st] = w;
+    out = w;
     return TP_OK;
 }
 
@@ -427,13 +451,51 @@ uint64_t plan_key(const std::vector<Req> &rq, int mode)
     return h;
 }
 
+// Release a plan and the graphs captured with it, once the work that reads
+// them has finished.
+void free_plan(Device &d, Plan *q)
+{
+    hipEventSynchronize(q->ready);
+    if (q->used) hipEventSynchronize(q->last_use);
+    for (uint64_t gk : q->graph_keys) {
+        auto g = d.graphs.find(gk);
+        if (g == d.graphs.end()) continue;
+        hipGraphExecDestroy(g->second.exec);
+        hipGraphDestroy(g->second.graph);
+        hipFree(g->second.ws.buf);
+        d.graphs.erase(g);
+    }
+    hipFree(q->dbuf);
+    hipHostFree(q->pinned);
+    hipEventDestroy(q->ready);
+    hipEventDestroy(q->last_use);
+    delete q;
+}
+
+// Order a use of plan p on stream st after its previous use on another stream
+// (the plan's tables, graphs and their workspaces are shared by all uses).
+int begin_use(Plan &p, hipStream_t st)
+{
+    if (p.made_on != st) TP_HIP(hipStreamWaitEvent(st, p.ready, 0));
+    if (p.used && p.last_stream != st) TP_HIP(hipStreamWaitEvent(st, p.last_use, 0));
+    return TP_OK;
+}
+
+int end_use(Plan &p, hipStream_t st)
+{
+    TP_HIP(hipEventRecord(p.last_use, st));
+    p.last_stream = st;
+    p.used = true;
+    return TP_OK;
+}
+
 int build_plan(Device &d, const std::vector<Req> &rq, int mode, hipStream_t st, Plan *&out)
 {
     const uint64_t key = plan_key(rq, mode);
     auto it = d.plans.find(key);
     if (it != d.plans.end()) {
         out = it->second;
-        if (out->made_on != st) TP_HIP(hipStreamWaitEvent(st, out->ready, 0));
+        d.lru.splice(d.lru.end(), d.lru, out->lru_pos);   // most recently used last
         return TP_OK;
     }
     Plan *p = new Plan();
@@ -445,7 +507,7 @@ int build_plan(Device &d, const std::vector<Req> &rq, int mode, hipStream_t st, 
     // order the samples by binning scheme (stable), one group per scheme
     std::vector<size_t> order(rq.size());
     for (size_t r = 0; r < order.size(); ++r) order[r] = r;
-    auto scheme = [&](size_t r) { return ks[r].kind[0] * 4 + ks[r].kind[1]; };
+    auto scheme = [&](size_t r) { return (ks[r].kind[0] * 4 + ks[r].kind[1]) * 2 + (ks[r].olo >= 0 ? 1 : 0); };
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return scheme(a) < scheme(b); });
     int64_t v = 0;
     for (size_t r : order) {
@@ -457,10 +519,13 @@ int build_plan(Device &d, const std::vector<Req> &rq, int mode, hipStream_t st, 
         v += (k.n + 255) & ~int64_t(255);
         const int sidx = (int)p->hs.size();
         p->hs.push_back(k);
-        if (p->groups.empty() || p->groups.back().k0 != k.kind[0] || p->groups.back().k1 != k.kind[1]) {
+        const bool ord = k.olo >= 0;
+        if (p->groups.empty() || p->groups.back().k0 != k.kind[0] || p->groups.back().k1 != k.kind[1] ||
+            p->groups.back().ord != ord) {
             Group g;
             g.k0 = k.kind[0];
             g.k1 = k.kind[1];
+            g.ord = ord;
             g.sbeg = sidx;
             g.vbeg = k.vstart;
             p->groups.push_back(g);
@@ -495,22 +560,18 @@ int build_plan(Device &d, const std::vector<Req> &rq, int mode, hipStream_t st, 
     p->dedges = reinterpret_cast<double *>(static_cast<char *>(p->dbuf) + ((sb + 255) & ~size_t(255)));
     TP_HIP(hipMemcpyAsync(p->dbuf, p->pinned, tot, hipMemcpyHostToDevice, st));
     TP_HIP(hipEventCreateWithFlags(&p->ready, hipEventDisableTiming));
+    TP_HIP(hipEventCreateWithFlags(&p->last_use, hipEventDisableTiming));
     TP_HIP(hipEventRecord(p->ready, st));
     p->made_on = st;
     d.plans[key] = p;
-    d.lru.push_back(key);
-    if (d.lru.size() > 256) {
+    p->lru_pos = d.lru.insert(d.lru.end(), key);
+    if (d.lru.size() > MAX_PLANS) {
+        // least recently used: freed (with its graphs) after its last use
         const uint64_t old = d.lru.front();
         d.lru.pop_front();
         Plan *q = d.plans[old];
-        // the plan may still be read by enqueued work: wait for it
-        hipEventSynchronize(q->ready);
-        hipDeviceSynchronize();
-        hipFree(q->dbuf);
-        hipHostFree(q->pinned);
-        hipEventDestroy(q->ready);
-        delete q;
         d.plans.erase(old);
+        free_plan(d, q);
     }
     out = p;
     return TP_OK;
@@ -549,7 +610,7 @@ int launch_plan(Device &d, const Plan &p, const std::vector<tp_tuning> &gtu, int
     kp.xlist = ws.xlist;
     kp.xcount = ws.xcount;
     kp.xdone = ws.xdone;
-    kp.xcap = XCAP;
+    kp.xcap = (uint32_t)ws.cap;
     kp.mode = mode;
     for (size_t gi = 0; gi < p.groups.size(); ++gi) {
         if (only >= 0 && (size_t)only != gi) continue;
@@ -586,7 +647,7 @@ int launch_plan(Device &d, const Plan &p, const std::vector<tp_tuning> &gtu, int
         kp.hist_stride = g.hist_stride;
         kp.edge_doubles = g.edge_doubles;
         kp.range = range;
-        TP_HIP(launch_pass(p.dtype, prec, mode, epl, g.k0, g.k1, kp, (int)grid, tu.block, lds, st));
+        TP_HIP(launch_pass(p.dtype, prec, mode, epl, g.k0, g.k1, g.ord, kp, (int)grid, tu.block, lds, st));
     }
     if (timed) {
         TP_HIP(hipEventRecord(e1, st));
@@ -602,10 +663,10 @@ int launch_plan(Device &d, const Plan &p, const std::vector<tp_tuning> &gtu, int
         const uint32_t m = std::min<uint32_t>(cnt, 4096);
         std::vector<uint64_t> lst(m);
         if (m) TP_HIP(hipMemcpy(lst.data(), ws.xlist, m * sizeof(uint64_t), hipMemcpyDeviceToHost));
-        int why[6] = { 0, 0, 0, 0, 0, 0 };
-        for (uint64_t e : lst) why[std::min<int>(5, (int)(e >> 60))]++;
-        std::fprintf(stderr, "tp_debug: %u deferred (validity %d, sign %d, axis0 %d, axis1 %d, order %d)", cnt,
-                     why[1], why[2], why[3], why[4], why[5]);
+        int why[7] = { 0, 0, 0, 0, 0, 0, 0 };
+        for (uint64_t e : lst) why[std::min<int>(6, (int)(e >> 60))]++;
+        std::fprintf(stderr, "tp_debug: %u deferred (validity %d, sign %d, axis0 %d, axis1 %d, order %d, "
+                     "first pass %d)", cnt, why[1], why[2], why[3], why[4], why[5], why[6]);
         for (uint32_t k = 0; k < std::min<uint32_t>(m, 8); ++k)
             std::fprintf(stderr, " [s%d e%lld w%d]", (int)((lst[k] >> 40) & 0xfffff),
                          (long long)(lst[k] & ((1ull << 40) - 1)), (int)(lst[k] >> 60));
@@ -680,7 +741,8 @@ std::string group_key(const Plan &p, const Group &g, int prec)
     int nb = 0;
     while ((int64_t(1) << nb) < g.vend - g.vbeg) ++nb;
     char buf[160];
-    std::snprintf(buf, sizeof buf, "g_d%d_p%d_k%d%d_n2^%d_h%d", p.dtype, prec, g.k0, g.k1, nb, g.hist_stride);
+    std::snprintf(buf, sizeof buf, "g_d%d_p%d_k%d%d%s_n2^%d_h%d", p.dtype, prec, g.k0, g.k1, g.ord ? "o" : "", nb,
+                  g.hist_stride);
     return buf;
 }
 
@@ -725,6 +787,8 @@ int run(const std::vector<Req> &rq, int prec, int mode, const tp_tuning *tuning,
     Plan *p = nullptr;
     rc = build_plan(d, rq, mode, st, p);
     if (rc) return rc;
+    rc = begin_use(*p, st);
+    if (rc) return rc;
     const std::vector<tp_tuning> gtu = resolve_tunings(d, *p, rq, prec, tuning);
     if (flags & TP_BATCH_GRAPH) {
         uint64_t gk = plan_key(rq, mode);
@@ -733,8 +797,9 @@ int run(const std::vector<Req> &rq, int prec, int mode, const tp_tuning *tuning,
         auto it = d.graphs.find(gk);
         if (it == d.graphs.end()) {
             GraphEntry ge;
-            rc = new_workspace(st, ge.ws);
+            rc = new_workspace(list_capacity(p->vtotal), st, ge.ws);
             if (rc) return rc;
+            TP_HIP(hipStreamSynchronize(st));
             hipStream_t cap;
             TP_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
             TP_HIP(hipStreamWaitEvent(cap, p->ready, 0));
@@ -752,6 +817,7 @@ int run(const std::vector<Req> &rq, int prec, int mode, const tp_tuning *tuning,
             ge.graph = g;
             TP_HIP(hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0));
             it = d.graphs.emplace(gk, ge).first;
+            p->graph_keys.push_back(gk);
         }
         const bool timed = g_timing.on && !g_timing.ring.empty();
         if (timed) TP_HIP(hipEventRecord(g_timing.ring[g_timing.next].first, st));
@@ -761,12 +827,14 @@ int run(const std::vector<Req> &rq, int prec, int mode, const tp_tuning *tuning,
             g_timing.next = (g_timing.next + 1) % g_timing.ring.size();
             g_timing.used = std::min(g_timing.used + 1, g_timing.ring.size());
         }
-        return TP_OK;
+        return end_use(*p, st);
     }
     Workspace ws;
-    rc = get_workspace(d, st, ws);
+    rc = get_workspace(d, st, list_capacity(p->vtotal), ws);
     if (rc) return rc;
-    return launch_plan(d, *p, gtu, prec, mode, ws, st);
+    rc = launch_plan(d, *p, gtu, prec, mode, ws, st);
+    if (rc) return rc;
+    return end_use(*p, st);
 }
 
 // exact ratio num/den of integers, rounded (long double division, then to double)
@@ -970,7 +1038,8 @@ int tp_autotune(const tp_sample *samples, int32_t nsamples, int32_t precision, v
     Plan *p = nullptr;
     Workspace ws;
     rc = build_plan(d, rq, 0, st, p);
-    if (!rc) rc = get_workspace(d, st, ws);
+    if (!rc) rc = begin_use(*p, st);
+    if (!rc) rc = get_workspace(d, st, list_capacity(p->vtotal), ws);
     // time ``trials`` runs of ``reps`` launches of group g with shape t; best run, ms per launch
     auto measure = [&](size_t g, const tp_tuning &t, int trials, int reps, float &ms) -> int {
         const std::vector<tp_tuning> gtu(p->groups.size(), t);
@@ -1077,6 +1146,7 @@ int tp_autotune(const tp_sample *samples, int32_t nsamples, int32_t precision, v
     g_timing.on = was_on;
     hipEventDestroy(a);
     hipEventDestroy(b);
+    if (p && !rc) rc = end_use(*p, st);
     if (rc) return rc;
     // the whole request's entry (for callers that pass it explicitly): the
     // largest group's shape, or the single shape that won
@@ -1193,12 +1263,7 @@ int tp_release(void)
     for (auto &kv : g_dev) {
         Device &d = kv.second;
         for (auto &w : d.ws) hipFree(w.second.buf);
-        for (auto &p : d.plans) {
-            hipFree(p.second->dbuf);
-            hipHostFree(p.second->pinned);
-            hipEventDestroy(p.second->ready);
-            delete p.second;
-        }
+        for (auto &p : d.plans) free_plan(d, p.second);
         for (auto &g : d.graphs) {
             hipGraphExecDestroy(g.second.exec);
             hipGraphDestroy(g.second.graph);

@@ -36,7 +36,8 @@ struct EvOut {
     int cls;      // CLS_* (CLS_DEFER: exact tier)
     int bin;      // combined bin, -1 out of range
     int t2;       // float64 recheck of the sign was needed
-    int why;      // deferred at: 1 validity, 2 sign, 3 first axis, 4 second axis, 5 order
+    int why;      // deferred at: 1 validity, 2 sign, 3 first axis, 4 second axis, 5 order,
+                  // 6 first pass (eval_lean)
     double ct;    // C_T^inv estimate
 };
 
@@ -514,6 +515,180 @@ __device__ __forceinline__ EvOut eval_event(const Tin (&q)[4][4], int tag, const
     }
 }
 
+// ------------------------------------------------------------ first pass
+// A lean evaluation of one event for float32 storage and a binning scheme
+// with a plane angle: the same quantities as eval_event (validity, minors,
+// sign, covectors, |cos theta| invariants, mass), computed branch-free, with
+// the error of each angle bounded by one combined expression.  Every
+// decision it returns is certified; ``ok`` is false where a bound does not
+// settle one, or where an input lies outside the ranges the bounds assume,
+// and the event then goes to the later tiers (double-word, exact integers).
+//
+// Ranges: with float32 inputs every exact intermediate of degree k in the
+// components is a multiple of 2^(-149 k), so nothing below degree 7 falls into
+// the subnormal range; W <= 2^64 keeps every intermediate finite, and the
+// degree-12 product D of the plane angle is required to be >= 2^-1000.  The
+// factor (1 +- eps_1)(1 +- eps_2) of D is taken to first order with the
+// constant 0.574 = (1 - sqrt(3/4)) / (1/4) * 1.07, valid for eps_1 + eps_2 <= 1/8.
+//
+// Plane angle (notation of bin_absphi_bv): with the term-by-term bounds eX,
+// eS_i of the full evaluation, eps_i = eS_i/|S_i^| with eps_1 + eps_2 <= 1/8
+// (so |sqrt(S1 S2 / D^) - 1| <= 0.574 (eps_1 + eps_2) + u) and the certified
+// reciprocal square root r (|r sqrt(D^) - 1| <= rel), the true
+// cos Phi = -X / sqrt(S1 S2) (|cos Phi| <= 1: the C_i lie in the space-like
+// complement of P) satisfies
+//   |v^ - cos Phi| <= eX r + rel + 0.575 (eps_1 + eps_2) + 1.6 u,
+// and eps_1 + eps_2 <= 1.0001 r^2 (eS1 |S2^| + eS2 |S1^|); evaluated with the
+// constant 0.58 and 4 u (roundings of the bound itself and of v^ +- eps), and
+// required to be at most 1/16 (which keeps eps_1 + eps_2 below 1/8).  This
+// replaces the separate bound on D and the ratio's error terms of the full
+// evaluation by one expression.
+//
+// |cos theta|: with the magnitude bounds of bin_abscos (24, 32, 10 u W^2 ...)
+// and the same steps, using 24 w_s/sqrt(A B) <= 0.672 (32 w_s^2/A + 10/B),
+//   |v^ - |cos theta|| <= 1.246 u W^2 (32 w_s^2 B + 10 A) r^2 + rel + 1.6 u,
+// evaluated as u W^2 (40 w_s^2 B + 13 A) r^2 + rel + 4 u, at most 1/16.
+//
+// A bin is certified when v^ - eps and v^ + eps pass the same edges.
+__device__ __forceinline__ double rsqrt_lean(double D, double &rel, bool &ok)
+{
+    const double r0 = __builtin_amdgcn_rsq(D);
+    const double t = D * r0;
+    const double rho = fma(-t, r0, 1.0);
+    const double r = fma(0.5 * r0, rho, r0);
+    ok = ok && (dabs(rho) <= 0x1p-10) && (D >= 0x1p-1000);
+    rel = fma(0.5 * rho, rho, 3.0 * U64);
+    return r;
+}
+
+// cos|Phi| bin: #{k in 1..n-1 : cos Phi <= c_k}
+__device__ __forceinline__ int absphi_lean(const double (&m01)[6], const double (&m23)[6], double M1, double M2s,
+                                           const double (&P)[4], double W, const double *e, int n, bool &ok)
+{
+    double C1[4], C2[4];
+    covector(P, m01, C1);
+    covector(P, m23, C2);
+    const double X = fma(-C1[3], C2[3], fma(-C1[2], C2[2], fma(-C1[1], C2[1], C1[0] * C2[0])));
+    const double S1 = fma(-C1[3], C1[3], fma(-C1[2], C1[2], fma(-C1[1], C1[1], C1[0] * C1[0])));
+    const double S2 = fma(-C2[3], C2[3], fma(-C2[2], C2[2], fma(-C2[1], C2[1], C2[0] * C2[0])));
+    const double D = S1 * S2;
+    double rel;
+    bool good = (S1 < 0.0) && (S2 < 0.0);
+    const double r = rsqrt_lean(D, rel, good);
+    const double v = -X * r;
+    // term-by-term bounds of bin_absphi_bv
+    const double A1 = (dabs(C1[0]) + dabs(C1[1])) + (dabs(C1[2]) + dabs(C1[3]));
+    const double A2 = (dabs(C2[0]) + dabs(C2[1])) + (dabs(C2[2]) + dabs(C2[3]));
+    const double k = (7.2 * U64) * W;
+    const double eC1 = fma(k, M1, TINY), eC2 = fma(k, M2s, TINY);
+    const double uA1 = (4.02 * U64) * A1, uA2 = (4.02 * U64) * A2;
+    const double eX = fma(eC2, A1, fma(eC1, A2, fma(4.0 * eC1, eC2, uA1 * A2)));
+    const double eS1 = fma(2.0 * eC1, A1, fma(4.0 * eC1, eC1, uA1 * A1));
+    const double eS2 = fma(2.0 * eC2, A2, fma(4.0 * eC2, eC2, uA2 * A2));
+    // eps_1 + eps_2 = eS1/|S1| + eS2/|S2| <= 1.0001 r^2 (eS1 |S2| + eS2 |S1|)
+    const double q = fma(eS1, -S2, eS2 * -S1);
+    const double eps = fma(eX, r, fma(0.58 * (r * r), q, rel + 4.0 * U64));
+    good = good && (eps <= 0.0625);
+    // bin = #{k : cos Phi <= c_k}: certified when both ends pass the same edges
+    int j, jlo;
+    count_edges<true>(v + eps, v - eps, e, n, j, jlo);
+    ok = ok && good && j == jlo;
+    return j;
+}
+
+// |cos theta| bin of kernel slot 0: #{k in 1..n-1 : |cos| >= e_k}
+__device__ __forceinline__ int abscos_lean(const double (&x)[4][4], double w0, const double (&P)[4], double M2,
+                                           double WW, const double *e, int n, bool &ok)
+{
+    const double PPs = mink(P, x[0]);
+    const double dss = mink(x[0], x[0]);
+    const double Nn = fma(PPs, P[0], -(M2 * x[0][0]));
+    const double A = fma(PPs, PPs, -(M2 * dss));
+    const double B = fma(P[3], P[3], fma(P[2], P[2], P[1] * P[1]));
+    bool good = (A > 0.0) && (B > 0.0);
+    double rel;
+    const double r = rsqrt_lean(A * B, rel, good);
+    const double v = dabs(Nn) * r;
+    const double T = (r * r) * fma((40.0 * w0) * w0, B, 13.0 * A);
+    const double eps = fma(U64 * WW, T, rel + 4.0 * U64);
+    good = good && (eps <= 0.0625);
+    // bin = #{k : |cos| >= e_k}: certified when both ends pass the same edges
+    int j, jhi;
+    count_edges<false>(v - eps, v + eps, e, n, j, jhi);
+    ok = ok && good && j == jhi;
+    return j;
+}
+
+template <int KIND>
+__device__ __forceinline__ int axis_lean(const double (&x)[4][4], const double (&w)[4], double WW,
+                                         const double *, const double *, double, double, const double (&P)[4],
+                                         double M2, int nb, int sl, const double *ed, double glo, double ginv,
+                                         bool &ok)
+{
+    static_assert(KIND == AX_MASS, "mass axis only");
+    (void)WW;
+    (void)P;
+    (void)M2;
+    bool sure = true;
+    const int j = bin_mass(x, w, sl, ed, nb, glo, ginv, sure);
+    ok = ok && sure;
+    return j;
+}
+
+// The first pass over one float32 event.  On ok: cls (CLS_I .. CLS_IV) and
+// bin (-1: outside the binned range).  The axes that read the components
+// (mass, |cos theta|) are evaluated before the minors so that the components
+// are no longer live during the plane angle.
+template <int K0, int K1, bool ORD>
+__device__ __forceinline__ void eval_lean(const float (&q)[4][4], int tag, const Seg &g, int &cls, int &bin,
+                                          bool &ok)
+{
+    double x[4][4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) x[s][c] = (double)q[s][c];
+    double w[4], P[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) w[s] = (dabs(x[s][0]) + dabs(x[s][1])) + (dabs(x[s][2]) + dabs(x[s][3]));
+    const double W = (w[0] + w[1]) + (w[2] + w[3]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) P[c] = (x[0][c] + x[1][c]) + (x[2][c] + x[3][c]);
+    const double M2 = fma(-P[3], P[3], fma(-P[2], P[2], fma(-P[1], P[1], P[0] * P[0])));
+    const double Emin = fmin(fmin(x[0][0], x[1][0]), fmin(x[2][0], x[3][0]));
+    const double WW = W * W;
+    // validity as in eval_event, and the range the bounds assume
+    ok = (tag == 0 || tag == 1) && Emin >= 0.0 && P[0] > 0.0 && M2 > fma(11.0 * U64, WW, TINY) && W <= 0x1p64;
+    if constexpr (ORD) {   // identical particles to be ordered (every sample of the launch)
+        const bool o = g.olo == 0 ? order_pair<0>(x, w, P, W, g.odir) : order_pair<1>(x, w, P, W, g.odir);
+        ok = ok && o;
+    }
+    int j0 = 0, j1 = 0;
+    if constexpr (K0 == AX_MASS) j0 = axis_lean<K0>(x, w, WW, nullptr, nullptr, 0, 0, P, M2, g.nb0, g.slots0, g.e0,
+                                                    g.glo0, g.ginv0, ok);
+    if constexpr (K1 == AX_MASS) j1 = axis_lean<K1>(x, w, WW, nullptr, nullptr, 0, 0, P, M2, g.nb1, g.slots1, g.e1,
+                                                    g.glo1, g.ginv1, ok);
+    if constexpr (K0 == AX_ABSCOS) j0 = abscos_lean(x, w[0], P, M2, WW, g.e0, g.nb0, ok);
+    if constexpr (K1 == AX_ABSCOS) j1 = abscos_lean(x, w[0], P, M2, WW, g.e1, g.nb1, ok);
+    double m01[6], m23[6];
+    minors_f64<true>(x[0], x[1], m01);
+    minors_f64<true>(x[2], x[3], m23);
+    const double M1 = l1norm6(m01), M2s = l1norm6(m23);
+    double det;
+    ok = ok && det_f64<true>(m01, m23, det, M1 * M2s);
+    const double ct = g.sigma > 0 ? det : -det;
+    cls = tag == 0 ? (ct > 0.0 ? CLS_I : CLS_II) : (ct < 0.0 ? CLS_III : CLS_IV);
+    if constexpr (K0 == AX_ABSPHI) j0 = absphi_lean(m01, m23, M1, M2s, P, W, g.e0, g.nb0, ok);
+    if constexpr (K1 == AX_ABSPHI) j1 = absphi_lean(m01, m23, M1, M2s, P, W, g.e1, g.nb1, ok);
+    bool oor = j0 < 0;
+    int b = j0 < 0 ? 0 : j0;
+    if constexpr (K1 != AX_NONE) {
+        oor = oor || j1 < 0;
+        b = b * g.nb1 + (j1 < 0 ? 0 : j1);
+    }
+    bin = oor ? -1 : b;
+}
+
 __device__ __forceinline__ uint32_t wave_count(bool p)
 {
     return (uint32_t)__popcll(__ballot(p));
@@ -618,9 +793,17 @@ struct SegIO {
 // events outside every bin), then NSTAT statistics words.
 __device__ __forceinline__ int lds_stats(int nbtot) { return (nbtot + 2) * 4; }
 
+// Whether binned float32 passes with a plane angle take the first pass
+// (eval_lean) before the full evaluation.
+template <typename Tin, int MODE, int K0, int K1>
+constexpr bool lean_pass()
+{
+    return MODE == 0 && sizeof(Tin) == 4 && (K0 == AX_ABSPHI || K1 == AX_ABSPHI);
+}
+
 // One tile: EPL consecutive events per lane, the lane's first at segment
 // offset ``loc``; ``len`` events in the segment, which starts at event ev0.
-template <typename Tin, int PREC, int MODE, int EPL, int K0, int K1>
+template <typename Tin, int PREC, int MODE, int EPL, int K0, int K1, bool ORD>
 __device__ __forceinline__ void process_tile(const KParams &kp, int s, const SegIO &io, const Seg &g,
                                              const Tin (&q)[EPL][4][4], const int (&tg)[EPL], uint32_t loc,
                                              uint32_t len, int64_t ev0, uint32_t *myhist, int srow,
@@ -632,7 +815,25 @@ __device__ __forceinline__ void process_tile(const KParams &kp, int s, const Seg
         const uint32_t li = loc + e;
         const bool in = li < len;
         EvOut o;
-        if (in) {
+        bool done = false;
+        if constexpr (lean_pass<Tin, MODE, K0, K1>()) {
+            {
+                // first pass; the rare events it does not settle go to the
+                // later tiers
+                int lc = 0, lb = 0;
+                bool ok;
+                eval_lean<K0, K1, ORD>(q[e], tg[e], g, lc, lb, ok);
+                const bool badtag = tg[e] != 0 && tg[e] != 1;
+                o.cls = !in ? -1 : badtag ? CLS_INVALID : ok ? lc : CLS_DEFER;
+                o.bin = in ? lb : -1;
+                o.t2 = 0;
+                o.why = 6;
+                o.ct = 0.0;
+                done = true;
+            }
+        }
+        if (done) {
+        } else if (in) {
             o = eval_event<Tin, PREC, K0, K1>(q[e], tg[e], g);
         } else {
             o.cls = -1;
@@ -696,7 +897,7 @@ constexpr bool prefetch_tiles()
 
 // The event loop of one segment: ``len`` events of sample s from event ev0,
 // addressed by 32-bit offsets (the host caps a workgroup's range).
-template <typename Tin, int PREC, int MODE, int EPL, int K0, int K1>
+template <typename Tin, int PREC, int MODE, int EPL, int K0, int K1, bool ORD>
 __device__ __forceinline__ void run_segment(const KParams &kp, int s, const SegIO &io, const Seg &g,
                                             int64_t ev0, uint32_t len, uint32_t *myhist, int srow,
                                             WaveCounts &wc)
@@ -717,10 +918,10 @@ __device__ __forceinline__ void run_segment(const KParams &kp, int s, const SegI
         for (uint32_t t0 = 0; t0 < len; t0 += 2 * step) {
             const uint32_t t1 = t0 + step;
             load_scalar<Tin, 1>(io.S, ev0, t1 + lane0, last, qb, tb);
-            process_tile<Tin, PREC, MODE, 1, K0, K1>(kp, s, io, g, qa, ta, t0 + lane0, len, ev0, myhist, srow, wc);
+            process_tile<Tin, PREC, MODE, 1, K0, K1, ORD>(kp, s, io, g, qa, ta, t0 + lane0, len, ev0, myhist, srow, wc);
             if (t1 >= len) break;
             load_scalar<Tin, 1>(io.S, ev0, t1 + step + lane0, last, qa, ta);
-            process_tile<Tin, PREC, MODE, 1, K0, K1>(kp, s, io, g, qb, tb, t1 + lane0, len, ev0, myhist, srow, wc);
+            process_tile<Tin, PREC, MODE, 1, K0, K1, ORD>(kp, s, io, g, qb, tb, t1 + lane0, len, ev0, myhist, srow, wc);
         }
         return;
     }
@@ -737,12 +938,12 @@ __device__ __forceinline__ void run_segment(const KParams &kp, int s, const SegI
             for (uint32_t t = 0; t < nfull; t += 2) {
                 const uint32_t n1 = t + 1 < nfull ? t + 1 : nfull - 1;
                 load_vector<Tin, EPL>(io.S, ev0, n1 * step + lane0, qb, tb);
-                process_tile<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, qa, ta, t * step + lane0, len, ev0, myhist,
+                process_tile<Tin, PREC, MODE, EPL, K0, K1, ORD>(kp, s, io, g, qa, ta, t * step + lane0, len, ev0, myhist,
                                                            srow, wc);
                 if (t + 1 >= nfull) break;
                 const uint32_t n2 = t + 2 < nfull ? t + 2 : nfull - 1;
                 load_vector<Tin, EPL>(io.S, ev0, n2 * step + lane0, qa, ta);
-                process_tile<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, qb, tb, (t + 1) * step + lane0, len, ev0,
+                process_tile<Tin, PREC, MODE, EPL, K0, K1, ORD>(kp, s, io, g, qb, tb, (t + 1) * step + lane0, len, ev0,
                                                            myhist, srow, wc);
             }
         }
@@ -751,7 +952,7 @@ __device__ __forceinline__ void run_segment(const KParams &kp, int s, const SegI
             Tin q[EPL][4][4];
             int tg[EPL];
             load_vector<Tin, EPL>(io.S, ev0, t * step + lane0, q, tg);
-            process_tile<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, q, tg, t * step + lane0, len, ev0, myhist, srow,
+            process_tile<Tin, PREC, MODE, EPL, K0, K1, ORD>(kp, s, io, g, q, tg, t * step + lane0, len, ev0, myhist, srow,
                                                        wc);
         }
     }
@@ -759,14 +960,14 @@ __device__ __forceinline__ void run_segment(const KParams &kp, int s, const SegI
         Tin q[EPL][4][4];
         int tg[EPL];
         load_scalar<Tin, EPL>(io.S, ev0, t0 + lane0, last, q, tg);
-        process_tile<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, q, tg, t0 + lane0, len, ev0, myhist, srow, wc);
+        process_tile<Tin, PREC, MODE, EPL, K0, K1, ORD>(kp, s, io, g, q, tg, t0 + lane0, len, ev0, myhist, srow, wc);
     }
 }
 
 // The pass over samples [kp.sbeg, kp.send), all of binning scheme (K0, K1):
 // each workgroup takes a contiguous range of the virtual event space, splits
 // it at sample boundaries, counts into LDS and flushes every segment.
-template <typename Tin, int PREC, int MODE, int EPL, int K0, int K1>
+template <typename Tin, int PREC, int MODE, int EPL, int K0, int K1, bool ORD>
 __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
 {
     constexpr bool BINNED = MODE == 0 && K0 != AX_NONE;
@@ -839,7 +1040,7 @@ __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
         __syncthreads();
 
         WaveCounts wc = { 0, 0, 0, 0 };
-        run_segment<Tin, PREC, MODE, EPL, K0, K1>(kp, s, io, g, ev0, (uint32_t)(ev1 - ev0), myhist, srow, wc);
+        run_segment<Tin, PREC, MODE, EPL, K0, K1, ORD>(kp, s, io, g, ev0, (uint32_t)(ev1 - ev0), myhist, srow, wc);
         if (!BINNED && MODE == 0 && lane == 0) {
             atomicAdd(&myhist[0], wc.c0);
             atomicAdd(&myhist[1], wc.c1);
@@ -880,36 +1081,42 @@ __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
 // ------------------------------------------------------------------ launchers
 namespace {
 template <typename T, int P, int M, int EPL, int K0, int K1>
-void launch_one(const KParams &kp, int grid, int block, size_t lds, hipStream_t st)
+void launch_one(bool ord, const KParams &kp, int grid, int block, size_t lds, hipStream_t st)
 {
     // with a plane angle binned, the float32-sign variant is the float64 one
     constexpr int PE = (K0 == AX_ABSPHI || K1 == AX_ABSPHI) ? 0 : P;
-    hipLaunchKernelGGL((tp_pass_kernel<T, PE, M, EPL, K0, K1>), dim3(grid), dim3(block), lds, st, kp);
+    // the first pass takes the ordering of identical particles as a
+    // compile-time step; the full evaluation decides it per sample
+    if (lean_pass<T, M, K0, K1>() && ord)
+        hipLaunchKernelGGL((tp_pass_kernel<T, PE, M, EPL, K0, K1, true>), dim3(grid), dim3(block), lds, st, kp);
+    else
+        hipLaunchKernelGGL((tp_pass_kernel<T, PE, M, EPL, K0, K1, false>), dim3(grid), dim3(block), lds, st, kp);
 }
 
 template <typename T, int P, int M, int K0, int K1>
-void launch_epl(int epl, const KParams &kp, int grid, int block, size_t lds, hipStream_t st)
+void launch_epl(int epl, bool ord, const KParams &kp, int grid, int block, size_t lds, hipStream_t st)
 {
     if constexpr (sizeof(T) == 4) {
         if (epl >= 4) {
-            launch_one<T, P, M, 4, K0, K1>(kp, grid, block, lds, st);
+            launch_one<T, P, M, 4, K0, K1>(ord, kp, grid, block, lds, st);
             return;
         }
     }
-    if (epl >= 2) launch_one<T, P, M, 2, K0, K1>(kp, grid, block, lds, st);
-    else launch_one<T, P, M, 1, K0, K1>(kp, grid, block, lds, st);
+    if (epl >= 2) launch_one<T, P, M, 2, K0, K1>(ord, kp, grid, block, lds, st);
+    else launch_one<T, P, M, 1, K0, K1>(ord, kp, grid, block, lds, st);
 }
 
 template <typename T, int P, int M>
-bool launch_scheme(int k0, int k1, int epl, const KParams &kp, int grid, int block, size_t lds, hipStream_t st)
+bool launch_scheme(int k0, int k1, int epl, bool ord, const KParams &kp, int grid, int block, size_t lds,
+                   hipStream_t st)
 {
     if constexpr (M == 1) {
         if (k0 != AX_NONE || k1 != AX_NONE) return false;
-        launch_epl<T, P, M, AX_NONE, AX_NONE>(epl, kp, grid, block, lds, st);
+        launch_epl<T, P, M, AX_NONE, AX_NONE>(epl, ord, kp, grid, block, lds, st);
         return true;
     } else {
 #define TP_CASE(A, B)                                                          \
-    case A * 4 + B: launch_epl<T, P, M, A, B>(epl, kp, grid, block, lds, st); return true;
+    case A * 4 + B: launch_epl<T, P, M, A, B>(epl, ord, kp, grid, block, lds, st); return true;
         switch (k0 * 4 + k1) {
             TP_CASE(AX_NONE, AX_NONE)
             TP_CASE(AX_ABSPHI, AX_NONE)
@@ -930,21 +1137,21 @@ bool launch_scheme(int k0, int k1, int epl, const KParams &kp, int grid, int blo
 }
 }  // namespace
 
-hipError_t launch_pass(int dtype, int prec, int mode, int epl, int k0, int k1, const KParams &kp, int grid,
+hipError_t launch_pass(int dtype, int prec, int mode, int epl, int k0, int k1, bool ord, const KParams &kp, int grid,
                        int block, size_t lds, hipStream_t st)
 {
     bool ok;
     if (dtype == 0) {
         if (prec == 1) {
-            ok = mode == 0 ? launch_scheme<float, 1, 0>(k0, k1, epl, kp, grid, block, lds, st)
-                           : launch_scheme<float, 1, 1>(k0, k1, epl, kp, grid, block, lds, st);
+            ok = mode == 0 ? launch_scheme<float, 1, 0>(k0, k1, epl, ord, kp, grid, block, lds, st)
+                           : launch_scheme<float, 1, 1>(k0, k1, epl, ord, kp, grid, block, lds, st);
         } else {
-            ok = mode == 0 ? launch_scheme<float, 0, 0>(k0, k1, epl, kp, grid, block, lds, st)
-                           : launch_scheme<float, 0, 1>(k0, k1, epl, kp, grid, block, lds, st);
+            ok = mode == 0 ? launch_scheme<float, 0, 0>(k0, k1, epl, ord, kp, grid, block, lds, st)
+                           : launch_scheme<float, 0, 1>(k0, k1, epl, ord, kp, grid, block, lds, st);
         }
     } else {
-        ok = mode == 0 ? launch_scheme<double, 0, 0>(k0, k1, epl, kp, grid, block, lds, st)
-                       : launch_scheme<double, 0, 1>(k0, k1, epl, kp, grid, block, lds, st);
+        ok = mode == 0 ? launch_scheme<double, 0, 0>(k0, k1, epl, ord, kp, grid, block, lds, st)
+                       : launch_scheme<double, 0, 1>(k0, k1, epl, ord, kp, grid, block, lds, st);
     }
     if (!ok) return hipErrorInvalidValue;
     return hipGetLastError();

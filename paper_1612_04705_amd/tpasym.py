@@ -224,8 +224,20 @@ def _check_counts(bn: Binning, counts, stats, ds: DeviceSample):
 
 
 # ------------------------------------------------------------------ entry points
-def compute(ds: DeviceSample, ch: _Channel, precision=TP_PREC_F64, want_ct=True, stats=None, stream=None):
-    """tp_compute: per-event class (int8) and C_T^inv (float64) on the device."""
+def raise_if_unresolved(stats, stream=None):
+    """Synchronise ``stream`` and raise if the statistics ``stats`` (device int64 [8]) count
+    events no tier could decide (components spanning more binary orders of magnitude than
+    the exact tier holds): their classes are then missing from the counts."""
+    (stream or torch.cuda.current_stream(stats.device)).synchronize()
+    n = int(stats[6].item())
+    if n:
+        raise TPError(f"{n} event(s) unresolved: components span beyond the exact tier's exponent range")
+
+
+def compute(ds: DeviceSample, ch: _Channel, precision=TP_PREC_F64, want_ct=True, stats=None, stream=None,
+            check=True):
+    """tp_compute: per-event class (int8) and C_T^inv (float64) on the device.  With ``check``
+    the call synchronises and raises if an event stayed unresolved."""
     lib = load()
     ev = ds.events()
     cls = torch.empty(ds.n, dtype=torch.int8, device=ds.tag.device)
@@ -238,12 +250,16 @@ def compute(ds: DeviceSample, ch: _Channel, precision=TP_PREC_F64, want_ct=True,
     _check(lib.tp_compute(ctypes.byref(ev), ctypes.byref(ch), int(precision), ctypes.c_void_p(cls.data_ptr()),
                           ctypes.c_void_p(ct.data_ptr()) if ct is not None else None,
                           ctypes.c_void_p(stats.data_ptr()), _stream(stream)))
+    if check:
+        raise_if_unresolved(stats, stream)
     return cls, ct, stats
 
 
 def bin(ds: DeviceSample, ch: _Channel, bn: Binning, precision=TP_PREC_F64, counts=None, stats=None,
-        stream=None):
-    """tp_bin: accumulate counts [(nbins+1)*4] and stats [8] (device int64 tensors, read as uint64)."""
+        stream=None, check=True):
+    """tp_bin: accumulate counts [(nbins+1)*4] and stats [8] (device int64 tensors, read as uint64).
+    With ``check`` the call synchronises and raises if an event stayed unresolved; without it
+    the call only enqueues."""
     lib = load()
     ev = ds.events()
     if counts is None or stats is None:
@@ -251,6 +267,8 @@ def bin(ds: DeviceSample, ch: _Channel, bn: Binning, precision=TP_PREC_F64, coun
     _check_counts(bn, counts, stats, ds)
     _check(lib.tp_bin(ctypes.byref(ev), ctypes.byref(ch), ctypes.byref(bn.b), int(precision),
                       ctypes.c_void_p(counts.data_ptr()), ctypes.c_void_p(stats.data_ptr()), _stream(stream)))
+    if check:
+        raise_if_unresolved(stats, stream)
     return counts, stats
 
 
@@ -269,10 +287,19 @@ class Batch:
             self.arr[i].counts = counts.data_ptr()
             self.arr[i].stats = stats.data_ptr()
 
-    def run(self, precision=TP_PREC_F32_RECHECK, tuning: Tuning | None = None, graph=False, stream=None):
+    def run(self, precision=TP_PREC_F32_RECHECK, tuning: Tuning | None = None, graph=False, stream=None,
+            check=False):
+        """tp_batch (enqueue only); with ``check`` also synchronise and raise on unresolved events."""
         _check(load().tp_batch(self.arr, len(self.items), int(precision),
                                ctypes.byref(tuning) if tuning is not None else None,
                                TP_BATCH_GRAPH if graph else 0, _stream(stream)))
+        if check:
+            self.check(stream)
+
+    def check(self, stream=None):
+        """Synchronise and raise if any sample's statistics count an unresolved event."""
+        for it in self.items:
+            raise_if_unresolved(it[4], stream)
 
     def autotune(self, precision=TP_PREC_F32_RECHECK, stream=None) -> Tuning:
         t = Tuning()

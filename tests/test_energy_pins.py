@@ -156,3 +156,42 @@ def test_d4pi_exact_tie_keeps_first_pair():
     # (2,3) = (11, -2, 0, 0) -> 117, (0,1) = (11, 2, 0, 0) -> 117, (0,3) = (11, 0, 0, 0) -> 121,
     # (2,1) = (11, 0, 0, 0) -> 121: (0,3) and (2,1) tie above the others; (0,3) comes first
     assert list(energy.d4pi_perm(comps4)) == [2]
+
+
+def test_column_pair_sums_brute_force():
+    """Every entry of the column pair-sum matrix against explicit pairs, and eq. (2)
+    from it against T_eq2 (several blocks, ragged last block)."""
+    rng = np.random.default_rng(5)
+    n, s = 41, 0.7
+    Y = rng.normal(size=(3, n))
+    G = (rng.uniform(size=(n, 4)) < 0.5).astype(np.float64)
+    psi = lambda i, j: math.exp(-sum((Y[k, i] - Y[k, j]) ** 2 for k in range(3)) / (2 * s * s))
+    M = energy.column_pair_sums(Y, G, s, block=16)
+    for c in range(4):
+        for d in range(4):
+            want = sum(G[i, c] * psi(i, j) * G[j, d] for i in range(n) for j in range(n) if i != j)
+            assert M[c, d] == pytest.approx(want, rel=1e-13)
+    lab = G[:, 0].astype(np.int64)
+    cols = np.stack([lab, 1 - lab], axis=1)
+    M2 = energy.column_pair_sums(Y, cols, s, block=16)
+    nx = int(lab.sum())
+    assert energy.T_eq2_columns(M2, 0, 1, nx, n - nx) == pytest.approx(energy.T_eq2(Y, lab, s), rel=1e-12)
+
+
+def test_eq3_from_column_pair_sums():
+    """eq. (3) from the column pair-sum matrix against the direct double sums."""
+    rng = np.random.default_rng(6)
+    main, mainb = rng.normal(size=(2, 23)), rng.normal(size=(2, 19))
+    bkg, bkgb = rng.normal(size=(2, 11)), rng.normal(size=(2, 9))
+    Y = np.concatenate([main, mainb, bkg, bkgb], axis=1)
+    sizes = [23, 19, 11, 9]
+    G = np.zeros((62, 4))
+    o = 0
+    for k, m in enumerate(sizes):
+        G[o:o + m, k] = 1
+        o += m
+    M = energy.column_pair_sums(Y, G, 0.9, block=8)
+    got = energy.T_eq3_columns(M, 0, 1, 2, 3, 23, 19, 11, 9, 4.0, 3.0)
+    assert got == pytest.approx(energy.T_eq3(main, mainb, bkg, bkgb, 4.0, 3.0, 0.9), rel=1e-12)
+    t1, t2, t3 = energy.T_eq3_columns(M, 0, 1, 2, 3, 23, 19, 11, 9, 4.0, 3.0, terms=True)
+    assert sum(t1) + sum(t2) - sum(t3) == pytest.approx(got, rel=1e-15)

@@ -50,6 +50,19 @@ def terms(Y, lab, sigma):
             energy.pair_sum(X, B, sigma, False) / (n * nb))
 
 
+def eq3_term_magnitude(main, main_bar, bkg, bkg_bar, b, b_bar, sigma):
+    """Sum of the magnitudes of the ten coefficient x pair-sum terms of eq. (3)."""
+    S = lambda A, B, same=False: energy.pair_sum(A, B, sigma, same)
+    n, nb, bs, bsb = main.shape[1], main_bar.shape[1], bkg.shape[1], bkg_bar.shape[1]
+    w, wb = n - b, nb - b_bar
+    t1 = [S(main, main, True), 2 * b / bs * S(main, bkg), b * (b + 1) / (bs * (bs - 1)) * S(bkg, bkg, True)]
+    t2 = [S(main_bar, main_bar, True), 2 * b_bar / bsb * S(main_bar, bkg_bar),
+          b_bar * (b_bar + 1) / (bsb * (bsb - 1)) * S(bkg_bar, bkg_bar, True)]
+    t3 = [S(main, main_bar), b_bar / bsb * S(main, bkg_bar), b / bs * S(bkg, main_bar),
+          b * b_bar / (bs * bsb) * S(bkg, bkg_bar)]
+    return sum(t1) / (2 * w * (w - 1)) + sum(t2) / (2 * wb * (wb - 1)) + sum(t3) / (w * wb)
+
+
 def test_coords_match_oracle(tp):
     ch, s = sample(3001, 80)
     ds = tp.DeviceSample.from_sample(s)
@@ -154,9 +167,10 @@ def test_eq3_against_oracle(tp):
     for k, (fm, fb) in enumerate(perms[:3]):
         fm, fb = fm.astype(bool), fb.astype(bool)
         w = energy.T_eq3(Yso[:, fm], Yso[:, ~fm], Ybo[:, fb], Ybo[:, ~fb], b, b_bar, 0.4)
-        # same term-magnitude tolerance as eq. (2), from the no-background terms
-        mag = sum(abs(t) for t in terms(Yso, fm.astype(np.uint8), 0.4))
-        assert abs(T[k] - w) <= 1e-4 * mag, (k, T[k], w)
+        # the same relative sum error as for eq. (2) (1e-5), applied to every one of
+        # the ten pair-sum terms of eq. (3) with its coefficient
+        mag = eq3_term_magnitude(Yso[:, fm], Yso[:, ~fm], Ybo[:, fb], Ybo[:, ~fb], b, b_bar, 0.4)
+        assert abs(T[k] - w) <= 1e-5 * mag, (k, T[k], w)
 
 
 def test_full_size_sampled_sums(tp):
@@ -181,7 +195,7 @@ def test_full_size_sampled_sums(tp):
     want_all = energy.pair_sum(Yo, Yo[:, pick], 0.3, False) - 64.0
     want_diag = energy.pair_sum(Yo[:, pick], Yo[:, pick], 0.3, True)
     assert abs(S[1, 1] - want_all) <= 1e-5 * want_all
-    assert abs(S[1, 0] - want_diag) <= 1e-5 * want_all
+    assert abs(S[1, 0] - want_diag) <= 1e-5 * want_diag
 
 
 D4PI_MASKS = [0b0011, 0b1001, 0b0110, 0b0111, 0b1011]     # m12, m14, m23, m123, m124 (Sect. 4.2, Table 1)
@@ -344,3 +358,98 @@ def test_raw_pair_sums_coordinate_counts(tp, D, C, nrow):
     for q in range(nrow):
         wq = Gf[:, q] @ V
         assert np.all(np.abs(S[:, 1 + q] - wq) <= 1e-5 * wq + 1e-9), q
+
+
+def test_T_at_scale_against_oracle(tp):
+    """T of eq. (2) and of eq. (3) at n = 30000 events, where the permutation spread of T
+    (~1e-5 at sigma = 0.3 GeV) is small against the three terms (~0.3 each): every
+    column against the oracle's column pair sums (float64, one pass over the pairs).
+
+    Tolerance from the pair sums' accuracy: the float32 tiles accumulate errors of
+    random sign, the sums come out within ~1e-9 relative at sigma = 0.3 (an emulation
+    of the float16 split and float32 accumulation on these coordinates); allowing
+    1e-8 relative on every sum, |delta T| <= 1e-8 x (sum of the terms' magnitudes).
+    The test checks that this tolerance is below 2 % of the permutation spread, so it
+    tells a right T from a wrong one, and that every p-value decision (permutation T
+    above the observed T) agrees where the two differ by more than twice the tolerance."""
+    import oracle
+    n, sigma, nperm = 30000, 0.3, 14
+    ch = synth.CHANNELS["D0_KKpipi"]
+    s = synth.generate(ch, n, 333, inj=synth.INJ_SGN)
+    comps, tag = s.numpy()
+    # the P-odd split of Sect. 5 ([I + IV] against [II + III]) from the oracle's classes
+    cls = oracle.run(comps, tag, ch.triple, ch.planes, want_events=True)["cls"]
+    assert np.all(cls < 4)
+    lab = ((cls == 0) | (cls == 3)).astype(np.uint8)
+    rng = np.random.default_rng(334)
+    labels = [lab] + [rng.permutation(lab) for _ in range(nperm)]
+    # eq. (3): the first 24000 events are the main samples, the last 6000 the
+    # background samples, flavour X = the split above; its permutations shuffle the
+    # flavour within the main and within the background events separately
+    nm = 24000
+    b3 = [(lab[:nm], lab[nm:])] + [(rng.permutation(lab[:nm]), rng.permutation(lab[nm:])) for _ in range(4)]
+    # device: all-ones, observed split, permutations (eq. 2); main, background and the
+    # triples (a, beta, a + beta) per flavour assignment (eq. 3)
+    cols2 = np.zeros((n, 32), dtype=np.uint8)
+    cols2[:, 0] = 1
+    for k, l in enumerate(labels):
+        cols2[:, 1 + k] = l
+    main = np.r_[np.ones(nm), np.zeros(n - nm)].astype(np.uint8)
+    cols3 = np.zeros((n, 32), dtype=np.uint8)
+    cols3[:, 0], cols3[:, 1] = main, 1 - main
+    triples = []
+    for k, (fm, fb) in enumerate(b3):
+        a = np.r_[fm, np.zeros(n - nm)].astype(np.uint8)
+        beta = np.r_[np.zeros(nm), fb].astype(np.uint8)
+        cols3[:, 2 + 3 * k], cols3[:, 3 + 3 * k], cols3[:, 4 + 3 * k] = a, beta, a + beta
+        triples.append((2 + 3 * k, 3 + 3 * k, 4 + 3 * k))
+    Yg = tp.coords(tp.DeviceSample.from_sample(s), MASKS, 1e-3)
+    sums2 = tp.pairsums(Yg, torch.from_numpy(cols2).cuda(), sigma, nrow=1)
+    sums3 = tp.pairsums(Yg, torch.from_numpy(cols3).cuda(), sigma, nrow=2)
+    torch.cuda.synchronize()
+    T2 = tp.energy_eq2(sums2, cols2.sum(axis=0), n, ones_row=0, ones_col=0)[1:1 + len(labels)]
+    nx_m = [int(fm.sum()) for fm, _ in b3]
+    nx_b = [int(fb.sum()) for _, fb in b3]
+    b, b_bar = 0.25 * nx_m[0], 0.25 * (nm - nx_m[0])
+    T3 = tp.energy_eq3(sums3, 0, 1, 0, 1, triples, nx_m[0], nm - nx_m[0], nx_b[0], (n - nm) - nx_b[0], b, b_bar)
+
+    # oracle: one pass over the pairs for every set that eq. (2) and eq. (3) use
+    Yo = energy.invariant_masses(comps, MASKS) * 1e-3
+    sets = []
+    for l in labels:
+        sets += [l, 1 - l]
+    for fm, fb in b3:
+        sets += [np.r_[fm, 0 * fb], np.r_[1 - fm, 0 * fb], np.r_[0 * fm, fb], np.r_[0 * fm, 1 - fb]]
+    M = energy.column_pair_sums(Yo, np.stack(sets, axis=1), sigma)
+    want2, mag2 = [], []
+    for k, l in enumerate(labels):
+        a, c = 2 * k, 2 * k + 1
+        nx = int(l.sum())
+        want2.append(energy.T_eq2_columns(M, a, c, nx, n - nx))
+        mag2.append(0.5 * M[a, a] / (nx * (nx - 1)) + 0.5 * M[c, c] / ((n - nx) * (n - nx - 1))
+                    + M[a, c] / (nx * (n - nx)))
+    want2, mag2 = np.array(want2), np.array(mag2)
+    tol2 = 1e-8 * mag2
+    spread2 = np.std(want2[1:])
+    print(f"[energy at scale] eq2: spread {spread2:.3e}, tol {tol2.max():.3e}, "
+          f"max |dT| {np.abs(np.array(T2) - want2).max():.3e}", flush=True)
+    assert tol2.max() <= 0.02 * spread2
+    assert np.all(np.abs(np.array(T2) - want2) <= tol2)
+    sure = np.abs(want2[1:] - want2[0]) > 2 * tol2.max()
+    assert np.array_equal((np.array(T2[1:]) > T2[0])[sure], (want2[1:] > want2[0])[sure])
+
+    # eq. (3) from the same pair sums, each term with the paper's coefficient
+    o = 2 * len(labels)
+    want3, mag3 = [], []
+    for k in range(len(b3)):
+        cols = (o + 4 * k, o + 4 * k + 1, o + 4 * k + 2, o + 4 * k + 3)
+        cnt = (nx_m[k], nm - nx_m[k], nx_b[k], (n - nm) - nx_b[k])
+        want3.append(energy.T_eq3_columns(M, *cols, *cnt, b, b_bar))
+        t1, t2, t3 = energy.T_eq3_columns(M, *cols, *cnt, b, b_bar, terms=True)
+        mag3.append(sum(abs(t) for t in t1 + t2 + t3))
+    want3, tol3 = np.array(want3), 1e-8 * np.array(mag3)
+    spread3 = np.std(want3[1:])
+    print(f"[energy at scale] eq3: spread {spread3:.3e}, tol {tol3.max():.3e}, "
+          f"max |dT| {np.abs(np.array(T3[:len(b3)]) - want3).max():.3e}", flush=True)
+    assert tol3.max() <= 0.02 * spread3
+    assert np.all(np.abs(np.array(T3[:len(b3)]) - want3) <= tol3)

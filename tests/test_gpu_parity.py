@@ -273,3 +273,90 @@ def test_event_order_does_not_matter(tp):
                     torch.cuda.synchronize()
                     out.append(([int(x) for x in u64(counts)], [int(x) for x in u64(stats)]))
                 assert out[0] == out[1], (axes, ident, prec)
+
+
+@pytest.mark.parametrize("wl,ch_name", [("lb_pkpipi_1e8_phi10xm8", "Lb_pKpipi"), ("d0_kkpipi_5e8_m32x32", "D0_KKpipi")])
+def test_scp_from_gpu_counts(tp, wl, ch_name):
+    """Binned S_CP of eq. (1) in both splits of Sect. 5 (P-even: [I+II] vs [III+IV];
+    P-odd: [I+IV] vs [II+III]) from the pass's counts, against the exact oracle
+    on the oracle's counts of the same events."""
+    spec = synth.workload_specs(wl, scale=2e-4 if wl.startswith("d0") else 1e-3)[0]
+    s = synth.make_sample(spec)
+    ch = spec.channel
+    comps, tag = s.numpy()
+    want = oracle.run(comps, tag, ch.triple, ch.planes, spec.axes)
+    got, stats = gpu_bin(tp, s, ch, spec.axes, tp.TP_PREC_F32_RECHECK)
+    assert got == want["counts"] and stats[6] == 0
+    c = np.array(got, dtype=np.int64).ravel()
+    w = np.array(want["counts"], dtype=object)
+    for mode in (0, 1):
+        S, chi2, ndf, p = tp.scp(c, mode)
+        if mode == 0:
+            x, xb = w[1:, 0] + w[1:, 1], w[1:, 2] + w[1:, 3]
+        else:
+            x, xb = w[1:, 0] + w[1:, 3], w[1:, 1] + w[1:, 2]
+        ws, wchi2, wndf, wp = exact.scp([int(v) for v in x], [int(v) for v in xb])
+        print(f"[scp] {wl} mode {mode}: chi2 {chi2:.4f} ndf {ndf} p {p:.4g}", flush=True)
+        assert ndf == wndf == len(x) - 1
+        np.testing.assert_allclose(S, ws, rtol=1e-12, atol=1e-15)
+        assert chi2 == pytest.approx(wchi2, rel=1e-12)
+        assert p == pytest.approx(wp, rel=1e-9, abs=1e-300)
+
+
+def test_graph_replay_after_plan_eviction(tp):
+    """More than 256 distinct requests evict the first request's launch plan (device
+    tables); a later graphed replay of that request must rebuild the plan and its graph,
+    not replay a graph whose tables were freed: counts stay bit-exact against the oracle."""
+    ch = synth.CHANNELS["Lb_ppipipi"]
+    axes = [synth.absphi_axis(10)]
+    s = synth.generate(ch, 3001, 41)
+    comps, tag = s.numpy()
+    want = oracle.run(comps, tag, ch.triple, ch.planes, axes)
+    ds = tp.DeviceSample.from_sample(s)
+    bn = tp.Binning(axes)
+    chan = tp.channel(ch.triple, ch.planes)
+    counts, stats = tp.new_counts(bn)
+    b = tp.Batch([(ds, chan, bn, counts, stats)])
+    b.run(tp.TP_PREC_F32_RECHECK, None, True, check=True)
+    c = [int(x) for x in u64(counts)]
+    assert [c[4 * r:4 * r + 4] for r in range(bn.nrows)] == want["counts"]
+    # 300 other requests (distinct counter buffers make distinct plans), each graphed
+    others = [tp.new_counts(bn) for _ in range(300)]
+    for oc, os_ in others:
+        tp.Batch([(ds, chan, bn, oc, os_)]).run(tp.TP_PREC_F32_RECHECK, None, True)
+    torch.cuda.synchronize()
+    for oc, _ in others[::37]:
+        c = [int(x) for x in u64(oc)]
+        assert [c[4 * r:4 * r + 4] for r in range(bn.nrows)] == want["counts"]
+    # the first request again, twice (its plan was evicted): counts accumulate
+    counts.zero_()
+    stats.zero_()
+    b.run(tp.TP_PREC_F32_RECHECK, None, True)
+    b.run(tp.TP_PREC_F32_RECHECK, None, True, check=True)
+    c = [int(x) for x in u64(counts)]
+    assert [c[4 * r:4 * r + 4] for r in range(bn.nrows)] == [[2 * v for v in row] for row in want["counts"]]
+
+
+def test_more_deferred_events_than_a_million(tp):
+    """2^20 + 4099 exactly coplanar events (Delta = 0) all defer to the exact tiers and
+    land in n_zero; nothing is unresolved (the deferral list holds every event of a launch)."""
+    n = (1 << 20) + 4099
+    rng = np.random.default_rng(12)
+    # four momenta in the x-y plane: every 4x4 determinant with a zero pz column vanishes
+    comps = np.zeros((4, 4, n), dtype=np.float32)
+    for slot in range(4):
+        px = rng.integers(-50, 50, size=n).astype(np.float32)
+        py = rng.integers(-50, 50, size=n).astype(np.float32)
+        comps[slot, 0] = np.sqrt(px.astype(np.float64) ** 2 + py.astype(np.float64) ** 2 + 140.0 ** 2).astype(np.float32)
+        comps[slot, 1], comps[slot, 2] = px, py
+    tag = (rng.uniform(size=n) < 0.5).astype(np.int8)
+    sample = synth.Sample(synth.CHANNELS["Lb_ppipipi"],
+                          [[torch.from_numpy(np.ascontiguousarray(comps[a][b])) for b in range(4)] for a in range(4)],
+                          torch.from_numpy(tag))
+    ch = synth.CHANNELS["Lb_ppipipi"]
+    for axes in ([], [synth.absphi_axis(10)]):
+        counts, stats = gpu_bin(tp, sample, ch, axes, tp.TP_PREC_F32_RECHECK)
+        print(f"[deferral] axes={len(axes)} stats={stats}", flush=True)
+        assert stats[0] == n and stats[1] == n and stats[6] == 0
+        assert stats[5] >= n                              # every event through the exact tiers
+        assert all(v == 0 for row in counts for v in row)
