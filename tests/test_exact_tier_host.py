@@ -162,3 +162,74 @@ def test_exact_tier_span_limit(hx):
     ev = [[float(c[sl, k, 0]) for k in range(4)] for sl in range(4)]
     got = decide(hx, ev, int(tag[0]), ch.triple, ch.planes, [], True)
     assert got[0] == 6
+
+
+def test_exact_tiers_under_sanitizers(hx, tmp_path):
+    """The exact and double-word tiers built with the address and undefined-behaviour
+    sanitizers (host build, g++) on random, extreme-boost, hand-built and degenerate
+    events: no sanitizer report, and the same decisions as the plain build (which the
+    tests above check against the oracle's Fractions)."""
+    import struct
+    exe = os.path.join(ROOT, "tests", "_build", "exact_san")
+    subprocess.run(["g++", "-O1", "-g", "-std=c++17", "-ffp-contract=off", "-fsanitize=address,undefined",
+                    "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-I",
+                    os.path.join(ROOT, "paper_1612_04705_amd", "csrc"), "-I", os.path.join(ROOT, "tests", "host"),
+                    os.path.join(ROOT, "tests", "host", "exact_sanitize_main.cpp"), "-o", exe], check=True)
+    reqs, want = [], []
+
+    def add(ev, tag, triple, planes, axes, is_f32):
+        inv = [0] * 4
+        for t, s in enumerate(planes):
+            inv[s] = t
+        k = [ev[planes[t]][c] for t in range(4) for c in range(4)]
+        sigma = perm_sign([6 - sum(triple), *triple]) * perm_sign(list(planes))
+        kinds, nb, sl, eds = [0, 0], [0, 0], [0, 0], []
+        for a, (kind, slots, edges) in enumerate(axes):
+            kinds[a], nb[a] = kind, len(edges) - 1
+            sl[a] = sum(1 << inv[s] for s in range(4) if slots & (1 << s)) if kind == synth.AXIS_MASS else \
+                (inv[slots] if kind == synth.AXIS_ABSCOS else 0)
+            eds.append(edges)
+        b = struct.pack("<16d10i", *k, int(is_f32), int(tag), sigma, len(axes), *kinds, *nb, *sl)
+        for e in eds:
+            b += struct.pack(f"<{len(e)}d", *e)
+        reqs.append(b)
+        c, bn = decide(hx, ev, tag, triple, planes, axes, is_f32)
+        fin = all(np.isfinite(v) for row in ev for v in row)
+        cd, bd = decide(hx, ev, tag, triple, planes, axes, is_f32, dw=True) if fin else (-1, None)
+        want.append((c, bn, cd, bd))
+
+    for chname, axes_fn, n, gamma in [
+            ("Lb_pKpipi", lambda ch: [synth.absphi_axis(10), synth.lb_mass03_axis(ch)], 40, None),
+            ("Lb_ppiKK", lambda ch: [synth.abscos_axis(0, 5), synth.absphi_axis(10)], 40, None),
+            ("D0_KKpipi", lambda ch: [synth.mass_axis((0, 1), 987.354, 1585.7, 32),
+                                      synth.mass_axis((2, 3), 279.14, 877.486, 32)], 30, None),
+            ("Lb_pKpipi", lambda ch: [synth.absphi_axis(10), synth.lb_mass03_axis(ch)], 20, 1e5)]:
+        ch = synth.CHANNELS[chname]
+        s = synth.generate(ch, n, 35, fixed_gamma=gamma) if gamma else synth.generate(ch, n, 35)
+        comps, tag = s.numpy()
+        c = comps.copy()
+        c[:, 3, :4] = 0.0                              # coplanar
+        c[1, 2, 5] = np.nan                            # invalid
+        c[:, 0, 6] = 0.0                               # space-like P
+        c[0, 1, 7] = np.float32(1e-40)                 # beyond the exponent span
+        ax = [(a.kind, a.slots, list(map(float, a.edges))) for a in axes_fn(ch)]
+        for i in range(n):
+            ev = [[float(c[sl_, k, i]) for k in range(4)] for sl_ in range(4)]
+            add(ev, int(tag[i]), ch.triple, ch.planes, ax, True)
+    from test_oracle_pins import _load_handbuilt, _as_sample
+    comps, tag = _as_sample(_load_handbuilt())
+    for axes in ([synth.absphi_axis(12)], [synth.Axis(synth.AXIS_MASS, np.array([5.0, 6.0, 7.0]), 0b1001)],
+                 [synth.Axis(synth.AXIS_ABSCOS, np.array([0.0, 0.2, 0.4, 0.6, 0.8, 1.0]), 0)]):
+        ax = [(a.kind, a.slots, list(map(float, a.edges))) for a in axes]
+        for i in range(comps.shape[2]):
+            ev = [[float(comps[sl_, k, i]) for k in range(4)] for sl_ in range(4)]
+            add(ev, int(tag[i]), (0, 1, 2), (0, 1, 2, 3), ax, True)
+    fin, fout = tmp_path / "req.bin", tmp_path / "res.bin"
+    fin.write_bytes(struct.pack("<i", len(reqs)) + b"".join(reqs))
+    r = subprocess.run([exe, str(fin), str(fout)], capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0 and "runtime error" not in r.stderr and "Sanitizer" not in r.stderr, r.stderr[-2000:]
+    res = np.frombuffer(fout.read_bytes(), dtype=np.int32).reshape(-1, 4)
+    assert len(res) == len(want)
+    for (c, bn, cd, bd), got in zip(want, res):
+        assert got[0] == c and (bn is None or got[1] == bn)
+        assert got[2] == cd and (bd is None or cd >= 4 or got[3] == bd)
