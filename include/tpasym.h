@@ -174,6 +174,24 @@ int tp_compute(const tp_events *ev, const tp_channel *ch, int32_t precision,
 int tp_bin(const tp_events *ev, const tp_channel *ch, const tp_binning *bn, int32_t precision,
            uint64_t *counts, tp_stats *stats, void *stream);
 
+/*
+ * tp_bin_noalloc -- tp_bin for callers that cannot allocate device memory
+ * (code under HIP graph capture, fixed-memory serving loops): the same
+ * arguments, outputs and results, but the launch tables, the exact tier's
+ * counters and its deferral list live in a file-scope device array of the
+ * library (32 MiB + 4 KiB, held on each device it runs on until the process
+ * ends), and no hipMalloc, hipFree or other allocating call is made.
+ *   Limits per call: ev->n <= 2^22 events (larger samples: call once per chunk;
+ *   counts accumulate) and at most 384 doubles of edge data (a MASS axis takes
+ *   3 (nbins + 1), the others nbins + 1); beyond them TP_ERANGE, nothing enqueued.
+ *   Launch shape: fixed (256 threads, 8 workgroups per compute unit).
+ *   Every call on one device shares the array and overwrites it at its start:
+ *   calls that overlap on one device (several streams or threads) race, and
+ *   must be ordered by the caller.
+ */
+int tp_bin_noalloc(const tp_events *ev, const tp_channel *ch, const tp_binning *bn, int32_t precision,
+                   uint64_t *counts, tp_stats *stats, void *stream);
+
 /* One row of asymmetries.  Value/sigma pairs:
  *   A_T      = (N_I - N_II) / (N_I + N_II)
  *   Abar_T   = (N_III - N_IV) / (N_III + N_IV)

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtpasym.so")
 
-SOURCES = ["tp_pass.hip", "tp_exact.hip", "tp_energy.hip", "tp_host.cpp"]
+SOURCES = ["tp_pass.hip", "tp_exact.hip", "tp_energy.hip", "tp_noalloc.hip", "tp_host.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # every fused multiply-add is written explicitly: the error bounds count roundings

@@ -17,6 +17,7 @@
 
 #include "../../include/tpasym.h"
 #include "tp_kernel.h"
+#include "tp_noalloc.h"
 
 namespace tpk {
 hipError_t launch_pass(int dtype, int prec, int mode, int epl, int k0, int k1, bool ord, const KParams &kp, int grid,
@@ -325,10 +326,24 @@ void square_bounds(double e, double &lo, double &hi)
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-// Fill one KSample (kernel order = channel planes).
+// Edge data of one launch in a fixed host array (no heap allocation).
+struct FixedEdges {
+    double v[NA_EDGES];
+    int n = 0;
+    bool overflow = false;
+    size_t size() const { return (size_t)n; }
+    void push_back(double x)
+    {
+        if (n < NA_EDGES) v[n++] = x;
+        else overflow = true;
+    }
+};
+
+// Fill one KSample (kernel order = channel planes); its edge data is appended
+// to ``edges`` (std::vector<double> or FixedEdges).
+template <class Edges>
 void fill_sample(KSample &k, const tp_events &ev, const tp_channel &ch, const tp_binning *bn,
-                 uint64_t *counts, tp_stats *stats, int8_t *cls_out, double *ct_out,
-                 std::vector<double> &edges)
+                 uint64_t *counts, tp_stats *stats, int8_t *cls_out, double *ct_out, Edges &edges)
 {
     std::memset(&k, 0, sizeof k);
     // Identical particles without a binned plane angle: any kernel order is
@@ -405,16 +420,19 @@ void fill_sample(KSample &k, const tp_events &ev, const tp_channel &ch, const tp
                 for (int s = 0; s < 4; ++s)
                     if (ax.slots & (1 << s)) m |= 1 << inv[s];
                 k.slots[a] = m;
-                std::vector<double> lo(ax.nbins + 1), hi(ax.nbins + 1);
-                for (int e = 0; e <= ax.nbins; ++e) square_bounds(ax.edges[e], lo[e], hi[e]);
-                edges.insert(edges.end(), lo.begin(), lo.end());
-                edges.insert(edges.end(), hi.begin(), hi.end());
-                edges.insert(edges.end(), ax.edges, ax.edges + ax.nbins + 1);
+                // lower bounds of e_k^2, then upper bounds, then the edges
+                for (int side = 0; side < 2; ++side)
+                    for (int e = 0; e <= ax.nbins; ++e) {
+                        double lo, hi;
+                        square_bounds(ax.edges[e], lo, hi);
+                        edges.push_back(side == 0 ? lo : hi);
+                    }
+                for (int e = 0; e <= ax.nbins; ++e) edges.push_back(ax.edges[e]);
                 k.guess_lo[a] = ax.edges[0];
                 k.guess_inv[a] = ax.nbins / (ax.edges[ax.nbins] - ax.edges[0]);
             } else {
                 k.slots[a] = ax.kind == TP_AXIS_ABSCOS ? inv[ax.slots] : 0;
-                edges.insert(edges.end(), ax.edges, ax.edges + ax.nbins + 1);
+                for (int e = 0; e <= ax.nbins; ++e) edges.push_back(ax.edges[e]);
             }
         }
     }
@@ -577,15 +595,51 @@ int build_plan(Device &d, const std::vector<Req> &rq, int mode, hipStream_t st, 
     return TP_OK;
 }
 
-void defaults(Device &d, tp_tuning &t, int64_t vtotal)
+void defaults(tp_tuning &t)
 {
     if (t.block != 256 && t.block != 512) t.block = 256;
     if (t.wg_per_cu < 1 || t.wg_per_cu > 16) t.wg_per_cu = 4;
     const int waves = t.block / 64;
     if (t.lds_copies < 1 || t.lds_copies > waves) t.lds_copies = waves;
     if (t.unroll != 1 && t.unroll != 2 && t.unroll != 4) t.unroll = 1;
-    (void)d;
-    (void)vtotal;
+}
+
+// One pass launch over the samples of group g with launch shape ``tu``;
+// ``kp`` carries the plan's tables and the deferral workspace.
+int launch_group(int cus, const Group &g, tp_tuning tu, int dtype, int prec, int mode, KParams kp, hipStream_t st)
+{
+    const int64_t nv = g.vend - g.vbeg;
+    defaults(tu);
+    const int epl = dtype == TP_F32 ? tu.unroll : std::min(tu.unroll, 2);
+    const int64_t tile = (int64_t)epl * tu.block;
+    int copies = tu.lds_copies;
+    size_t hist_bytes = 0;
+    for (;;) {
+        hist_bytes = ((size_t)(8 + copies * g.hist_stride) * 4 + 15) & ~size_t(15);
+        if (hist_bytes + (size_t)g.edge_doubles * 8 <= LDS_LIMIT || copies == 1) break;
+        --copies;
+    }
+    const size_t lds = hist_bytes + (size_t)g.edge_doubles * 8;
+    if (lds > LDS_LIMIT) return fail(TP_ERANGE, "histogram does not fit in LDS");
+    int64_t grid = (int64_t)cus * tu.wg_per_cu;
+    const int64_t need = (nv + tile - 1) / tile;
+    if (grid > need) grid = need;
+    if (grid < 1) grid = 1;
+    int64_t range = (nv + grid - 1) / grid;
+    range = (range + tile - 1) / tile * tile;
+    // the kernel forms in-segment offsets in 32 bits: at most 2^26 events a workgroup
+    range = std::min<int64_t>(range, int64_t(1) << 26);
+    grid = (nv + range - 1) / range;
+    kp.sbeg = g.sbeg;
+    kp.send = g.send;
+    kp.vbeg = g.vbeg;
+    kp.vend = g.vend;
+    kp.lds_copies = copies;
+    kp.hist_stride = g.hist_stride;
+    kp.edge_doubles = g.edge_doubles;
+    kp.range = range;
+    TP_HIP(launch_pass(dtype, prec, mode, epl, g.k0, g.k1, g.ord, kp, (int)grid, tu.block, lds, st));
+    return TP_OK;
 }
 
 // Launch the plan's pass kernels (one per scheme group, each with its own
@@ -617,37 +671,8 @@ int launch_plan(Device &d, const Plan &p, const std::vector<tp_tuning> &gtu, int
         const Group &g = p.groups[gi];
         const int64_t nv = g.vend - g.vbeg;
         if (nv <= 0) continue;
-        tp_tuning tu = gtu[gi];
-        defaults(d, tu, nv);
-        const int epl = p.dtype == TP_F32 ? tu.unroll : std::min(tu.unroll, 2);
-        const int64_t tile = (int64_t)epl * tu.block;
-        int copies = tu.lds_copies;
-        size_t hist_bytes = 0;
-        for (;;) {
-            hist_bytes = ((size_t)(8 + copies * g.hist_stride) * 4 + 15) & ~size_t(15);
-            if (hist_bytes + (size_t)g.edge_doubles * 8 <= LDS_LIMIT || copies == 1) break;
-            --copies;
-        }
-        const size_t lds = hist_bytes + (size_t)g.edge_doubles * 8;
-        if (lds > LDS_LIMIT) return fail(TP_ERANGE, "histogram does not fit in LDS");
-        int64_t grid = (int64_t)d.cus * tu.wg_per_cu;
-        const int64_t need = (nv + tile - 1) / tile;
-        if (grid > need) grid = need;
-        if (grid < 1) grid = 1;
-        int64_t range = (nv + grid - 1) / grid;
-        range = (range + tile - 1) / tile * tile;
-        // the kernel forms in-segment offsets in 32 bits: at most 2^26 events a workgroup
-        range = std::min<int64_t>(range, int64_t(1) << 26);
-        grid = (nv + range - 1) / range;
-        kp.sbeg = g.sbeg;
-        kp.send = g.send;
-        kp.vbeg = g.vbeg;
-        kp.vend = g.vend;
-        kp.lds_copies = copies;
-        kp.hist_stride = g.hist_stride;
-        kp.edge_doubles = g.edge_doubles;
-        kp.range = range;
-        TP_HIP(launch_pass(p.dtype, prec, mode, epl, g.k0, g.k1, g.ord, kp, (int)grid, tu.block, lds, st));
+        const int rc = launch_group(d.cus, g, gtu[gi], p.dtype, prec, mode, kp, st);
+        if (rc) return rc;
     }
     if (timed) {
         TP_HIP(hipEventRecord(e1, st));
@@ -764,7 +789,7 @@ std::vector<tp_tuning> resolve_tunings(Device &d, const Plan &p, const std::vect
             auto it = d.tuned.find(group_key(p, p.groups[g], prec));
             if (it != d.tuned.end()) t = it->second;
         }
-        defaults(d, t, 0);
+        defaults(t);
         out[g] = t;
     }
     return out;
@@ -939,6 +964,62 @@ int tp_bin(const tp_events *ev, const tp_channel *ch, const tp_binning *bn, int3
     if (ev->n == 0) return TP_OK;
     std::vector<Req> rq{ Req{ ev, ch, bn, counts, stats, nullptr, nullptr } };
     return run(rq, precision, 0, nullptr, 0, static_cast<hipStream_t>(stream));
+}
+
+int tp_bin_noalloc(const tp_events *ev, const tp_channel *ch, const tp_binning *bn, int32_t precision,
+                   uint64_t *counts, tp_stats *stats, void *stream)
+{
+    int rc = check_events(ev, precision);
+    if (rc) return rc;
+    rc = check_channel(ch);
+    if (rc) return rc;
+    rc = check_binning(bn);
+    if (rc) return rc;
+    rc = check_identical(ch, bn);
+    if (rc) return rc;
+    if (!counts || !stats) return fail(TP_EINVAL, "counts and stats are required");
+    if (ev->n > NA_MAX_EVENTS) return fail(TP_ERANGE, "tp_bin_noalloc takes at most 2^22 events per call");
+    if (ev->n == 0) return TP_OK;
+    KSample k;
+    FixedEdges ed;
+    fill_sample(k, *ev, *ch, bn, counts, stats, nullptr, nullptr, ed);
+    if (ed.overflow) return fail(TP_ERANGE, "tp_bin_noalloc holds at most 384 doubles of edge data per call");
+    k.vstart = 0;
+    Group g;
+    g.k0 = k.kind[0];
+    g.k1 = k.kind[1];
+    g.ord = k.olo >= 0;
+    g.sbeg = 0;
+    g.send = 1;
+    g.vbeg = 0;
+    g.vend = (k.n + 255) & ~int64_t(255);
+    g.hist_stride = (k.nbtot + 2) * 4 + NSTAT;
+    g.edge_doubles = ed.n;
+    int dev = 0, cus = 0;
+    TP_HIP(hipGetDevice(&dev));
+    TP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    unsigned char *base = nullptr;
+    TP_HIP(noalloc_scratch(dev, &base));
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    TP_HIP(launch_noalloc_setup(k, ed.v, ed.n, base, st));
+    KParams kp;
+    std::memset(&kp, 0, sizeof kp);
+    kp.samples = reinterpret_cast<const KSample *>(base + NA_SAMPLE_OFF);
+    kp.edges = reinterpret_cast<const double *>(base + NA_EDGES_OFF);
+    kp.xlist = reinterpret_cast<uint64_t *>(base + NA_LIST_OFF);
+    kp.xcount = reinterpret_cast<uint32_t *>(base + NA_COUNT_OFF);
+    kp.xdone = kp.xcount + 1;
+    kp.xcap = (uint32_t)NA_MAX_EVENTS;
+    kp.mode = 0;
+    tp_tuning tu;
+    tu.block = 256;
+    tu.wg_per_cu = 8;
+    tu.lds_copies = 4;
+    tu.unroll = 1;
+    rc = launch_group(cus > 0 ? cus : 256, g, tu, ev->dtype, precision, 0, kp, st);
+    if (rc) return rc;
+    TP_HIP(launch_exact(ev->dtype, 0, kp, EXACT_GRID, st));
+    return TP_OK;
 }
 
 int tp_batch(const tp_sample *samples, int32_t nsamples, int32_t precision, const tp_tuning *tuning,

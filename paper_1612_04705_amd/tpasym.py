@@ -89,6 +89,8 @@ def load():
         "tp_asym": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p],
         "tp_scp": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, P(ctypes.c_double),
                    P(ctypes.c_int64), P(ctypes.c_double)],
+        "tp_bin_noalloc": [P(_Events), P(_Channel), P(_Binning), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                           ctypes.c_void_p],
         "tp_batch": [P(_Sample), ctypes.c_int32, ctypes.c_int32, P(Tuning), ctypes.c_int32, ctypes.c_void_p],
         "tp_autotune": [P(_Sample), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, P(Tuning)],
         "tp_timing_enable": [ctypes.c_int32],
@@ -117,7 +119,7 @@ def load():
 
 
 def exported_symbols():
-    return ("tp_compute", "tp_bin", "tp_asym", "tp_scp", "tp_batch", "tp_autotune", "tp_timing_enable",
+    return ("tp_compute", "tp_bin", "tp_bin_noalloc", "tp_asym", "tp_scp", "tp_batch", "tp_autotune", "tp_timing_enable",
             "tp_timing_reset", "tp_timing_read", "tp_release", "tp_strerror", "tp_version", "tp_coords",
             "tp_pairsums", "tp_energy_eq2", "tp_energy_eq3")
 
@@ -267,6 +269,23 @@ def bin(ds: DeviceSample, ch: _Channel, bn: Binning, precision=TP_PREC_F64, coun
     _check_counts(bn, counts, stats, ds)
     _check(lib.tp_bin(ctypes.byref(ev), ctypes.byref(ch), ctypes.byref(bn.b), int(precision),
                       ctypes.c_void_p(counts.data_ptr()), ctypes.c_void_p(stats.data_ptr()), _stream(stream)))
+    if check:
+        raise_if_unresolved(stats, stream)
+    return counts, stats
+
+
+def bin_noalloc(ds: DeviceSample, ch: _Channel, bn: Binning, precision=TP_PREC_F64, counts=None, stats=None,
+                stream=None, check=True):
+    """tp_bin_noalloc: tp_bin without any device allocation by the library (at most 2^22 events
+    per call; calls on one device must not overlap)."""
+    lib = load()
+    ev = ds.events()
+    if counts is None or stats is None:
+        counts, stats = new_counts(bn, ds.tag.device)
+    _check_counts(bn, counts, stats, ds)
+    _check(lib.tp_bin_noalloc(ctypes.byref(ev), ctypes.byref(ch), ctypes.byref(bn.b), int(precision),
+                              ctypes.c_void_p(counts.data_ptr()), ctypes.c_void_p(stats.data_ptr()),
+                              _stream(stream)))
     if check:
         raise_if_unresolved(stats, stream)
     return counts, stats
