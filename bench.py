@@ -127,8 +127,10 @@ def energy_leg(n, nperm, dev, per_pass=126, cpu_events=0):
     Y = tpasym.coords(ds, masks, 1e-3)
     cls, _, _ = tpasym.compute(ds, tpasym.channel(ch.triple, ch.planes), tpasym.TP_PREC_F32_RECHECK)
     lab = ((cls == 0) | (cls == 3)).to(torch.uint8)
-    g = torch.Generator(device=dev)
-    g.manual_seed(1234)
+    # permutations drawn on the host (seeded numpy; random numbers are inputs of the
+    # library), one shuffled copy of the split per permutation column
+    rng = np.random.default_rng(1234)
+    lab_h = lab.cpu().numpy()
     ks = [min(per_pass, nperm - p0) for p0 in range(0, nperm, per_pass)]
     colsets = []
     for k in ks:
@@ -136,12 +138,11 @@ def energy_leg(n, nperm, dev, per_pass=126, cpu_events=0):
         C = 32 if ncol <= 32 else (64 if ncol <= 64 else 128)
         if ncol > 128:
             raise SystemExit("at most 126 permutations per launch")
-        cols = torch.zeros((n, C), dtype=torch.uint8, device=dev)
+        cols = np.zeros((n, C), dtype=np.uint8)
         cols[:, 0] = 1
-        cols[:, 1] = lab
-        for q in range(k):
-            cols[:, 2 + q] = lab[torch.randperm(n, generator=g, device=dev)]
-        colsets.append(cols.contiguous())
+        cols[:, 1] = lab_h
+        cols[:, 2:2 + k] = rng.permuted(np.broadcast_to(lab_h, (k, n)), axis=1).T
+        colsets.append(torch.from_numpy(cols).to(dev))
     sigma = 0.3
     tpasym.pairsums(Y, colsets[0], sigma)                      # warm-up
     torch.cuda.synchronize()
@@ -182,6 +183,12 @@ def energy_leg(n, nperm, dev, per_pass=126, cpu_events=0):
     valu_ops = 3.0 * npairs
     t_bound = (dist_flops + mfma_flops) / (MFMA_F16_PEAK_TFLOPS * 1e12) + valu_ops / (VALU_PEAK_TOPS * 1e12)
     C0 = colsets[0].shape[1]
+    # method-level bound, independent of how the kernel splits its work: psi once per
+    # unordered pair on the vector ALU (D differences, D multiply-adds, one exp:
+    # 2 D + 1 lane operations) and one multiply-add per pair and column (2 flops
+    # per column, on the float16 matrix cores at their dense peak)
+    t_method = ops / (VALU_PEAK_TOPS * 1e12) + sum(2.0 * c.shape[1] * pairs for c in colsets) / \
+        (MFMA_F16_PEAK_TFLOPS * 1e12)
     log(f"energy test: {n} events, {nperm} permutations in {len(ks)} launches of {C0} columns, "
         f"{sec * 1e3:.1f} ms, {sec * 1e3 / nperm:.2f} ms per permutation, T = {T_obs:.4e}")
     cpu = None
@@ -214,6 +221,8 @@ def energy_leg(n, nperm, dev, per_pass=126, cpu_events=0):
                          "valu_frac": valu_ops / sec / 1e12 / VALU_PEAK_TOPS,
                          "method_alu_tops": ops / sec / 1e12, "method_alu_frac": ops / sec / 1e12 / VALU_PEAK_TOPS,
                          "method_lane_ops_per_pair": 2 * D + 1,
+                         "method_bound": {"seconds": t_method, "frac": t_method / sec,
+                                          "per_pair": {"valu_lane_ops": 2 * D + 1, "mfma_f16_flops_per_column": 2}},
                          "dtype": "f16 x2 (distances, products), f32 (psi, tiles), f64 (sums)"},
             "T_obs": T_obs, "T_obs_spread_over_launches": max(T_obs_passes) - min(T_obs_passes),
             "p_value": float(np.count_nonzero(T_perm > T_obs)) / nperm,
@@ -244,22 +253,22 @@ def energy_bkg_leg(n, nperm, dev, bkg_frac=0.2, per_launch=41):
         labs.append(((cls == 0) | (cls == 3)).to(torch.uint8))
     Y = torch.cat(Ys, dim=1).contiguous()
     fm, fb = labs
-    g = torch.Generator(device=dev)
-    g.manual_seed(4321)
+    fm_h, fb_h = fm.cpu().numpy(), fb.cpu().numpy()
+    rng = np.random.default_rng(4321)
     ks = [min(per_launch, nperm - p0) for p0 in range(0, nperm, per_launch)]
     colsets = []
     for k in ks:
-        cols = torch.zeros((n, 128), dtype=torch.uint8, device=dev)
+        cols = np.zeros((n, 128), dtype=np.uint8)
         cols[:nm, 0] = 1
         cols[nm:, 1] = 1
         for q in range(k + 1):            # triple 0: the observed flavours
-            a = fm if q == 0 else fm[torch.randperm(nm, generator=g, device=dev)]
-            bt = fb if q == 0 else fb[torch.randperm(nb, generator=g, device=dev)]
+            a = fm_h if q == 0 else rng.permutation(fm_h)
+            bt = fb_h if q == 0 else rng.permutation(fb_h)
             cols[:nm, 2 + 3 * q] = a
             cols[nm:, 3 + 3 * q] = bt
             cols[:nm, 4 + 3 * q] = a
             cols[nm:, 4 + 3 * q] = bt
-        colsets.append(cols.contiguous())
+        colsets.append(torch.from_numpy(cols).to(dev))
     sigma = 0.3
     tpasym.pairsums(Y, colsets[0], sigma, nrow=2)               # warm-up
     torch.cuda.synchronize()
@@ -291,6 +300,141 @@ def energy_bkg_leg(n, nperm, dev, bkg_frac=0.2, per_launch=41):
             "T_obs": T_obs, "p_value": float(np.count_nonzero(T_perm > T_obs)) / nperm}
 
 
+def fp32_report(items, samples=None, max_events=None):
+    """The float32 tier measured on the given samples (tp_probe_f32): how often its
+    bound sends an event to the float64 recheck, its observed error against the
+    float64 contraction (relative to the sum of the Laplace terms' magnitudes and
+    to the value), and the raw float32 signs that are wrong, all of which must
+    fall among the rechecked events."""
+    import torch
+    from paper_1612_04705_amd import tpasym
+    U = 2.0 ** -53
+    n_tot = rech = wrong = wrong_out = uncertain = 0
+    rel_s, rel_v, ratio_max = [], [], 0.0
+    for it in items:
+        ds, ch = it[0], it[1]
+        if max_events is not None and ds.n > max_events:
+            ds = tpasym.DeviceSample([c[:max_events] for c in ds.comps], ds.tag[:max_events])
+        d32, b32, d64, s64 = tpasym.probe_f32(ds, ch)
+        d32 = d32.double()
+        b32 = b32.double()
+        err = (d32 - d64).abs()
+        certified = d64.abs() > 10 * U * s64          # the float64 sign is certain
+        rechecked = d32.abs() <= b32
+        bad = certified & (torch.sign(d32) != torch.sign(d64))
+        n_tot += ds.n
+        rech += int(rechecked.sum())
+        wrong += int(bad.sum())
+        wrong_out += int((bad & ~rechecked).sum())
+        uncertain += int((~certified).sum())
+        pos = s64 > 0
+        rel_s.append((err[pos] / s64[pos]).float())
+        nz = d64 != 0
+        rel_v.append((err[nz] / d64[nz].abs()).float())
+        # the bound holds: |d32 - d64| <= bound32 + 8.1 u S
+        ratio_max = max(ratio_max, float(((err - 8.1 * U * s64) / b32.clamp_min(1e-300)).max()))
+    rs, rv = torch.cat(rel_s), torch.cat(rel_v)
+    qs = torch.tensor([0.5, 0.99, 0.999], device=rs.device)
+
+    def pct(t):
+        # quantiles of a large tensor on a sorted sample (torch.quantile has a size cap)
+        t = t.sort().values
+        idx = (qs * (t.numel() - 1)).long()
+        return [float(t[i]) for i in idx] + [float(t[-1])]
+    return {"events": n_tot, "rechecked_frac": rech / n_tot,
+            "err_over_term_sum": dict(zip(("p50", "p99", "p999", "max"), pct(rs))),
+            "err_over_value": dict(zip(("p50", "p99", "p999", "max"), pct(rv))),
+            "raw_fp32_wrong_signs": wrong, "wrong_signs_outside_recheck": wrong_out,
+            "float64_sign_uncertain": uncertain, "max_err_over_bound": ratio_max}
+
+
+def scp_report(items, reps):
+    """Binned S_CP (eq. (1)) of every sample's counts in both splits of Sect. 5."""
+    import numpy as np
+    from paper_1612_04705_amd import tpasym
+    rows = []
+    for it in items:
+        c = it[3].cpu().numpy().view(np.uint64)
+        if not np.all(c % reps == 0):
+            raise SystemExit("accumulated counts are not a whole number of passes")
+        c = (c // reps).astype(np.int64)
+        if c.size <= 8:
+            continue
+        r = []
+        for mode in (0, 1):
+            _, chi2, ndf, pv = tpasym.scp(c, mode)
+            r += [round(float(chi2), 4), float(f"{pv:.4g}")]
+        rows.append(r + [int(ndf)])
+    return {"columns": ["chi2_P_even", "p_P_even", "chi2_P_odd", "p_P_odd", "ndf"], "per_sample": rows}
+
+
+def d0_leg(dev, steps, warmup):
+    """The largest single-sample workload: 5e8 D0 -> K+ K- pi+ pi- events, 32 x 32
+    bins in (m(K+K-), m(pi+pi-)), float32 storage: the float32 sign tier with the
+    float64 recheck is the path that runs here (no plane angle is binned)."""
+    import numpy as np
+    import torch
+    from paper_1612_04705_amd import synth, tpasym
+    t0 = time.time()
+    spec = synth.workload_specs("d0_kkpipi_5e8_m32x32")[0]
+    smp = synth.make_sample(spec, device=dev)
+    ds = tpasym.DeviceSample([smp.comps[a][b] for a in range(4) for b in range(4)], smp.tag)
+    del smp
+    n = ds.n
+    bn = tpasym.Binning(spec.axes)
+    ch = tpasym.channel(spec.channel.triple, spec.channel.planes)
+    counts, stats = tpasym.new_counts(bn, dev)
+    b = tpasym.Batch([(ds, ch, bn, counts, stats)])
+    torch.cuda.synchronize()
+    log(f"d0 leg: generated {n} events in {time.time() - t0:.1f}s")
+    b.autotune(tpasym.TP_PREC_F32_RECHECK)
+    for _ in range(warmup):
+        b.run(tpasym.TP_PREC_F32_RECHECK, None, True)
+    torch.cuda.synchronize()
+    tpasym.timing_enable(True)
+    tpasym.timing_reset()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        b.run(tpasym.TP_PREC_F32_RECHECK, None, True)
+    e1.record()
+    torch.cuda.synchronize()
+    kern_ms, _ = tpasym.timing_read()
+    tpasym.timing_enable(False)
+    ms = e0.elapsed_time(e1) / steps
+    b.check()
+    reps = warmup + steps
+    st = stats.cpu().numpy().view(np.uint64)
+    c32 = counts.cpu().numpy().view(np.uint64)
+    assert np.all(c32 % reps == 0)
+    c32 = c32 // reps
+    # the plain float64 request on the same events: identical counts
+    c64, s64 = tpasym.bin(ds, ch, bn, tpasym.TP_PREC_F64)
+    same = bool(np.array_equal(c64.cpu().numpy().view(np.uint64), c32))
+    scp = []
+    for mode in (0, 1):
+        _, chi2, ndf, pv = tpasym.scp(c32.astype(np.int64), mode)
+        scp.append({"split": "P-even" if mode == 0 else "P-odd", "chi2": float(chi2), "ndf": int(ndf),
+                    "p": float(pv)})
+    asym = tpasym.asym(c32.astype(np.int64))[0]
+    achieved = n * BYTES_F32 / (kern_ms / 1e3) / 1e9
+    log(f"d0 leg: {ms:.3f} ms/step, {n / (ms / 1e3):.3e} events/s, {achieved:.0f} GB/s, "
+        f"tier2 {int(st[4]) / reps / n:.2e}")
+    out = {"workload": "d0_kkpipi_5e8_m32x32", "events": n, "ms_per_step": ms, "value": n / (ms / 1e3),
+           "unit": "events/s", "dtype": "f32 sign tier, f64 recheck and bins",
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "bytes_per_event": BYTES_F32, "kernel_ms": kern_ms},
+           "tiers": {"tier2_frac": int(st[4]) / reps / n, "tier3_per_step": int(st[5]) / reps,
+                     "unresolved": int(st[6])},
+           "counts_equal_f64_request": same, "scp": scp,
+           "global": {"A_T": asym["A_T"][0], "Abar_T": asym["Abar_T"][0], "a_CP": asym["a_CP"][0],
+                      "a_P": asym["a_P"][0]},
+           "fp32": fp32_report([(ds, ch)], max_events=50_000_000)}
+    del ds, counts, stats, b, c64, s64
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -318,6 +462,10 @@ def main():
                     help="events of the bounded oracle timing beside the energy-test leg")
     ap.add_argument("--energy-bkg-perms", type=int, default=164,
                     help="permutations of the background-subtracted (eq. 3) leg, 41 per launch (0 skips it)")
+    ap.add_argument("--no-d0", action="store_true",
+                    help="skip the 5e8-event D0 -> K+ K- pi+ pi- leg (32 x 32 mass bins)")
+    ap.add_argument("--no-fp32-report", action="store_true",
+                    help="skip the measurement of the float32 tier's error on the workload")
     ap.add_argument("--copy-calib", action="store_true",
                     help="one extra untimed launch of the 1 GiB streaming reference (HBM byte-counter calibration)")
     args = ap.parse_args()
@@ -412,10 +560,12 @@ def main():
         t1.record(stream)
         torch.cuda.synchronize()
         f64_ms = t0.elapsed_time(t1) / f64_steps
-        # both paths must agree bit for bit
-        agree = all(np.array_equal(a[3].cpu().numpy().view(np.uint64) // reps,
-                                   b[3].cpu().numpy().view(np.uint64) // (f64_steps + 1))
-                    for a, b in zip(items, f64_items))
+        # both paths must agree bit for bit (whole numbers of passes on both sides)
+        agree = True
+        for a, b in zip(items, f64_items):
+            ca, cb = a[3].cpu().numpy().view(np.uint64), b[3].cpu().numpy().view(np.uint64)
+            agree = agree and bool(np.all(ca % reps == 0) and np.all(cb % (f64_steps + 1) == 0)
+                                   and np.array_equal(ca // reps, cb // (f64_steps + 1)))
         f64_leg = {"value": nevents / (f64_ms / 1e3), "unit": "events/s", "ms_per_step": f64_ms,
                    "counts_equal_fast_path": bool(agree)}
 
@@ -464,12 +614,18 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == tpasym.TP_PREC_F32_RECHECK and not f64_store else "f64",
+        # every binning scheme of the batched workload bins the plane angle, where the
+        # pass decides the sign and the bins in float64 (first pass, then double-word
+        # and exact integers) on the float32-stored events
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wl, "samples": len(samples), "events": nevents,
                    "storage": "f64" if f64_store else "f32",
                    "path": ("persistent batched pass, HIP graph" if graph else "persistent batched pass"),
-                   "precision": args.precision, "tuning": tuning_desc},
+                   "precision": args.precision,
+                   "arithmetic": "float64 certified tiers on float32 storage (plane-angle schemes: the float32 "
+                                 "sign tier does not run), double-word and exact integers for deferred events",
+                   "tuning": tuning_desc},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None,
                      "traffic": traffic,
@@ -481,6 +637,13 @@ def main():
         "paper_context": "energy test (different algorithm): 1e6 events, one permutation ~30 min on "
                          "NVIDIA M2070 / K40c (Sect. 6); no timing is given for the triple-product pass",
     }
+    out["scp"] = scp_report(items, reps)
+    if not args.no_fp32_report:
+        out["fp32_report"] = fp32_report(items)
+        log(f"fp32 report: {out['fp32_report']['rechecked_frac']:.2e} rechecked, "
+            f"{out['fp32_report']['raw_fp32_wrong_signs']} raw wrong signs, "
+            f"{out['fp32_report']['wrong_signs_outside_recheck']} outside the recheck")
+    batch.check()
     if not args.no_cpu:
         want = {}
         cpu, orc = cpu_baseline(samples, args.cpu_events, set(range(len(samples))))
@@ -496,6 +659,8 @@ def main():
             ok = ok and got == wantc
         out["parity_vs_oracle"] = {"samples_checked": len(orc), "counts_bit_exact": bool(ok)}
         log(f"cpu baseline {cpu['value']:.3e} events/s on {cpu['cores']} threads ({cpu['seconds']:.1f}s)")
+    if not args.no_d0:
+        out["d0_leg"] = d0_leg(dev, max(3, args.steps // 2), 2)
     if args.energy_events > 0:
         out["energy_test"] = energy_leg(int(args.energy_events), args.energy_perms, dev,
                                         cpu_events=0 if args.no_cpu else args.energy_cpu_events)

@@ -144,7 +144,8 @@ typedef struct {
                                  in the global row of the counts)                   */
     uint64_t n_tier2;         /* events that needed the float64 recheck of the sign
                                  (TP_PREC_F32_RECHECK only)                         */
-    uint64_t n_tier3;         /* events decided by the exact integer tier           */
+    uint64_t n_tier3;         /* events passed to the later tiers (double-word, then
+                                 exact integers)                                    */
     uint64_t n_unresolved;    /* events beyond the exact tier's range: an error     */
     uint64_t reserved;
 } tp_stats;
@@ -191,6 +192,18 @@ int tp_bin(const tp_events *ev, const tp_channel *ch, const tp_binning *bn, int3
  */
 int tp_bin_noalloc(const tp_events *ev, const tp_channel *ch, const tp_binning *bn, int32_t precision,
                    uint64_t *counts, tp_stats *stats, void *stream);
+
+/*
+ * tp_probe_f32 -- measurement of the float32 tier (float32 storage only): per
+ * event the float32 contraction C_T^inv (sign convention of tp_compute) from
+ * Kahan-FMA minors, its running forward error bound (the event is rechecked in
+ * float64 when |det32| <= bound32), the float64 contraction and the sum of the
+ * magnitudes of its six Laplace terms (the float64 value is within 8.1 u of
+ * that sum, u = 2^-53).  Certifies nothing: it reports the raw values.
+ *   det32, bound32: device float[n]; det64, scale64: device double[n].
+ */
+int tp_probe_f32(const tp_events *ev, const tp_channel *ch, float *det32, float *bound32, double *det64,
+                 double *scale64, void *stream);
 
 /* One row of asymmetries.  Value/sigma pairs:
  *   A_T      = (N_I - N_II) / (N_I + N_II)

@@ -23,6 +23,8 @@ namespace tpk {
 hipError_t launch_pass(int dtype, int prec, int mode, int epl, int k0, int k1, bool ord, const KParams &kp, int grid,
                        int block, size_t lds, hipStream_t st);
 hipError_t launch_exact(int dtype, int mode, const KParams &kp, int grid, hipStream_t st);
+hipError_t launch_probe(const KSample &k, float *det32, float *bound32, double *det64, double *scale64,
+                        hipStream_t st);
 }  // namespace tpk
 
 using namespace tpk;
@@ -52,6 +54,14 @@ int fail(int code, const std::string &msg)
 constexpr uint64_t XCAP_MIN = 1u << 16;
 constexpr uint64_t XCAP_MAX = 1ull << 31;
 constexpr int EXACT_GRID = 128;
+
+// Workgroups of the exact-tier launch (64 threads each, one listed event per
+// thread and pass over the list): more for larger launches, whose lists are
+// longer.
+int exact_grid(int64_t vtotal)
+{
+    return (int)std::min<int64_t>(EXACT_GRID, std::max<int64_t>(16, vtotal >> 16));
+}
 constexpr size_t MAX_PLANS = 256;        // launch plans kept per device
 constexpr size_t LDS_LIMIT = 64 * 1024;
 
@@ -697,7 +707,7 @@ int launch_plan(Device &d, const Plan &p, const std::vector<tp_tuning> &gtu, int
                          (long long)(lst[k] & ((1ull << 40) - 1)), (int)(lst[k] >> 60));
         std::fprintf(stderr, "\n");
     }
-    TP_HIP(launch_exact(p.dtype, mode, kp, EXACT_GRID, st));
+    TP_HIP(launch_exact(p.dtype, mode, kp, exact_grid(p.vtotal), st));
     return TP_OK;
 }
 
@@ -1018,7 +1028,24 @@ int tp_bin_noalloc(const tp_events *ev, const tp_channel *ch, const tp_binning *
     tu.unroll = 1;
     rc = launch_group(cus > 0 ? cus : 256, g, tu, ev->dtype, precision, 0, kp, st);
     if (rc) return rc;
-    TP_HIP(launch_exact(ev->dtype, 0, kp, EXACT_GRID, st));
+    TP_HIP(launch_exact(ev->dtype, 0, kp, exact_grid(g.vend), st));
+    return TP_OK;
+}
+
+int tp_probe_f32(const tp_events *ev, const tp_channel *ch, float *det32, float *bound32, double *det64,
+                 double *scale64, void *stream)
+{
+    int rc = check_events(ev, TP_PREC_F32_RECHECK);
+    if (rc) return rc;
+    rc = check_channel(ch);
+    if (rc) return rc;
+    if (!det32 || !bound32 || !det64 || !scale64) return fail(TP_EINVAL, "every output is required");
+    if (ev->n > (int64_t(1) << 31)) return fail(TP_ERANGE, "at most 2^31 events per call");
+    if (ev->n == 0) return TP_OK;
+    KSample k;
+    FixedEdges ed;
+    fill_sample(k, *ev, *ch, nullptr, nullptr, nullptr, nullptr, nullptr, ed);
+    TP_HIP(launch_probe(k, det32, bound32, det64, scale64, static_cast<hipStream_t>(stream)));
     return TP_OK;
 }
 

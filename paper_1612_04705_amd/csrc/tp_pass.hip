@@ -105,7 +105,7 @@ __device__ __forceinline__ bool det_f64(const double (&m01)[6], const double (&m
     return dabs(s) > bound;
 }
 
-__device__ __forceinline__ bool det_f32(const float x[4][4], float &det)
+__device__ __forceinline__ bool det_f32(const float x[4][4], float &det, float *bound_out = nullptr)
 {
     float m01[6], m23[6];
 #define TP_M(k, a, b)                                       \
@@ -129,6 +129,7 @@ __device__ __forceinline__ bool det_f32(const float x[4][4], float &det)
     // |s - det| <= 10.01 u S  + (subnormal / flush-to-zero terms) <= 2^-124 per minor
     const float bound = fmaf(10.5f * U32, S, fmaf(0x1p-120f, T, 0x1p-120f));
     det = s;
+    if (bound_out) *bound_out = bound;
     return fabsf(s) > bound;
 }
 
@@ -655,10 +656,10 @@ __device__ __forceinline__ void eval_lean(const float (&q)[4][4], int tag, const
 #pragma unroll
     for (int c = 0; c < 4; ++c) P[c] = (x[0][c] + x[1][c]) + (x[2][c] + x[3][c]);
     const double M2 = fma(-P[3], P[3], fma(-P[2], P[2], fma(-P[1], P[1], P[0] * P[0])));
-    const double Emin = fmin(fmin(x[0][0], x[1][0]), fmin(x[2][0], x[3][0]));
     const double WW = W * W;
     // validity as in eval_event, and the range the bounds assume
-    ok = (tag == 0 || tag == 1) && Emin >= 0.0 && P[0] > 0.0 && M2 > fma(11.0 * U64, WW, TINY) && W <= 0x1p64;
+    const bool epos = (x[0][0] >= 0.0) & (x[1][0] >= 0.0) & (x[2][0] >= 0.0) & (x[3][0] >= 0.0);
+    ok = (tag == 0 || tag == 1) && epos && P[0] > 0.0 && M2 > fma(11.0 * U64, WW, TINY) && W <= 0x1p64;
     if constexpr (ORD) {   // identical particles to be ordered (every sample of the launch)
         const bool o = g.olo == 0 ? order_pair<0>(x, w, P, W, g.odir) : order_pair<1>(x, w, P, W, g.odir);
         ok = ok && o;
@@ -674,8 +675,14 @@ __device__ __forceinline__ void eval_lean(const float (&q)[4][4], int tag, const
     minors_f64<true>(x[0], x[1], m01);
     minors_f64<true>(x[2], x[3], m23);
     const double M1 = l1norm6(m01), M2s = l1norm6(m23);
-    double det;
-    ok = ok && det_f64<true>(m01, m23, det, M1 * M2s);
+    // Laplace sum of det_f64 with its bound from the product of the minors' norms
+    double det = m01[0] * m23[5];
+    det = fma(-m01[1], m23[4], det);
+    det = fma(m01[2], m23[3], det);
+    det = fma(m01[3], m23[2], det);
+    det = fma(-m01[4], m23[1], det);
+    det = fma(m01[5], m23[0], det);
+    ok = ok && (dabs(det) > (10.0 * U64) * (M1 * M2s));
     const double ct = g.sigma > 0 ? det : -det;
     cls = tag == 0 ? (ct > 0.0 ? CLS_I : CLS_II) : (ct < 0.0 ? CLS_III : CLS_IV);
     if constexpr (K0 == AX_ABSPHI) j0 = absphi_lean(m01, m23, M1, M2s, P, W, g.e0, g.nb0, ok);
@@ -1078,6 +1085,38 @@ __global__ __launch_bounds__(512) void tp_pass_kernel(const KParams kp)
 
 }  // namespace
 
+// ---------------------------------------------------------- float32 tier probe
+// Per event, the float32 tier's contraction sigma * det[kernel rows] with its
+// running forward bound (what TP_PREC_F32_RECHECK certifies against), and the
+// float64 contraction with the sum S of the magnitudes of its Laplace terms
+// (its own error is below 8.1 u S): the measurement of the float32 error.
+__global__ __launch_bounds__(256) void tp_probe_kernel(const KSample k, float *det32, float *bound32,
+                                                       double *det64, double *scale64)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= k.n) return;
+    float q[4][4];
+    double x[4][4];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        q[t >> 2][t & 3] = static_cast<const float *>(k.p[t])[i];
+        x[t >> 2][t & 3] = (double)q[t >> 2][t & 3];
+    }
+    float d32, b32;
+    det_f32(q, d32, &b32);
+    double m01[6], m23[6], d64;
+    minors_f64<true>(x[0], x[1], m01);
+    minors_f64<true>(x[2], x[3], m23);
+    det_f64<true>(m01, m23, d64);
+    double S = dabs(m01[0]) * dabs(m23[5]);
+#pragma unroll
+    for (int t = 1; t < 6; ++t) S = fma(dabs(m01[t]), dabs(m23[5 - t]), S);
+    det32[i] = k.sigma > 0 ? d32 : -d32;
+    bound32[i] = b32;
+    det64[i] = k.sigma > 0 ? d64 : -d64;
+    scale64[i] = S;
+}
+
 // ------------------------------------------------------------------ launchers
 namespace {
 template <typename T, int P, int M, int EPL, int K0, int K1>
@@ -1136,6 +1175,14 @@ bool launch_scheme(int k0, int k1, int epl, bool ord, const KParams &kp, int gri
     }
 }
 }  // namespace
+
+hipError_t launch_probe(const KSample &k, float *det32, float *bound32, double *det64, double *scale64,
+                        hipStream_t st)
+{
+    const int64_t grid = (k.n + 255) / 256;
+    hipLaunchKernelGGL(tp_probe_kernel, dim3((unsigned)grid), dim3(256), 0, st, k, det32, bound32, det64, scale64);
+    return hipGetLastError();
+}
 
 hipError_t launch_pass(int dtype, int prec, int mode, int epl, int k0, int k1, bool ord, const KParams &kp, int grid,
                        int block, size_t lds, hipStream_t st)

@@ -91,6 +91,8 @@ def load():
                    P(ctypes.c_int64), P(ctypes.c_double)],
         "tp_bin_noalloc": [P(_Events), P(_Channel), P(_Binning), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                            ctypes.c_void_p],
+        "tp_probe_f32": [P(_Events), P(_Channel), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                         ctypes.c_void_p],
         "tp_batch": [P(_Sample), ctypes.c_int32, ctypes.c_int32, P(Tuning), ctypes.c_int32, ctypes.c_void_p],
         "tp_autotune": [P(_Sample), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, P(Tuning)],
         "tp_timing_enable": [ctypes.c_int32],
@@ -119,7 +121,7 @@ def load():
 
 
 def exported_symbols():
-    return ("tp_compute", "tp_bin", "tp_bin_noalloc", "tp_asym", "tp_scp", "tp_batch", "tp_autotune", "tp_timing_enable",
+    return ("tp_compute", "tp_bin", "tp_bin_noalloc", "tp_probe_f32", "tp_asym", "tp_scp", "tp_batch", "tp_autotune", "tp_timing_enable",
             "tp_timing_reset", "tp_timing_read", "tp_release", "tp_strerror", "tp_version", "tp_coords",
             "tp_pairsums", "tp_energy_eq2", "tp_energy_eq3")
 
@@ -289,6 +291,21 @@ def bin_noalloc(ds: DeviceSample, ch: _Channel, bn: Binning, precision=TP_PREC_F
     if check:
         raise_if_unresolved(stats, stream)
     return counts, stats
+
+
+def probe_f32(ds: DeviceSample, ch: _Channel, stream=None):
+    """tp_probe_f32: (det32, bound32, det64, scale64) device tensors, one value per event."""
+    lib = load()
+    ev = ds.events()
+    dev = ds.tag.device
+    d32 = torch.empty(ds.n, dtype=torch.float32, device=dev)
+    b32 = torch.empty(ds.n, dtype=torch.float32, device=dev)
+    d64 = torch.empty(ds.n, dtype=torch.float64, device=dev)
+    s64 = torch.empty(ds.n, dtype=torch.float64, device=dev)
+    _check(lib.tp_probe_f32(ctypes.byref(ev), ctypes.byref(ch), ctypes.c_void_p(d32.data_ptr()),
+                            ctypes.c_void_p(b32.data_ptr()), ctypes.c_void_p(d64.data_ptr()),
+                            ctypes.c_void_p(s64.data_ptr()), _stream(stream)))
+    return d32, b32, d64, s64
 
 
 class Batch:

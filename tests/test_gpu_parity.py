@@ -360,3 +360,30 @@ def test_more_deferred_events_than_a_million(tp):
         assert stats[0] == n and stats[1] == n and stats[6] == 0
         assert stats[5] >= n                              # every event through the exact tiers
         assert all(v == 0 for row in counts for v in row)
+
+
+@pytest.mark.parametrize("chname,gamma", [("D0_KKpipi", None), ("Lb_ppipipi", None), ("Lb_pKpipi", 300.0)])
+def test_fp32_tier_probe(tp, chname, gamma):
+    """The float32 tier's raw contraction (tp_probe_f32) against the float64 one and the
+    oracle: its running bound covers its error (|det32 - det64| <= bound32 + 8.1 u S),
+    every raw float32 sign that disagrees with the oracle's certified class lies among the
+    events the bound sends to the recheck, and the recheck fraction equals the pass's n_tier2
+    on the same events (global counts, TP_PREC_F32_RECHECK)."""
+    ch = synth.CHANNELS[chname]
+    s = synth.generate(ch, 20011, 61, fixed_gamma=gamma) if gamma else synth.generate(ch, 20011, 61)
+    comps, tag = s.numpy()
+    want = oracle.run(comps, tag, ch.triple, ch.planes, want_events=True)
+    cls = np.asarray(want["cls"])
+    ds = tp.DeviceSample.from_sample(s)
+    d32, b32, d64, s64 = [t.cpu().numpy().astype(np.float64) for t in tp.probe_f32(ds, tp.channel(ch.triple, ch.planes))]
+    assert np.all(np.abs(d32 - d64) <= b32 + 8.1 * 2.0 ** -53 * s64)
+    # eq. (4): the class fixes the sign of C_T for M (tag 0) and of -Cbar_T ... i.e. sign(C_T^inv)
+    sgn = np.where(np.isin(cls, (0, 3)), 1.0, np.where(np.isin(cls, (1, 2)), -1.0, 0.0))
+    decided = sgn != 0
+    wrong = decided & (np.sign(d32) != sgn)
+    rechecked = np.abs(d32) <= b32
+    print(f"[fp32 probe] {chname} gamma={gamma}: rechecked {rechecked.mean():.2e}, raw wrong signs "
+          f"{int(wrong.sum())}", flush=True)
+    assert not np.any(wrong & ~rechecked)
+    counts, stats = gpu_bin(tp, s, ch, [], tp.TP_PREC_F32_RECHECK)
+    assert stats[4] == int(rechecked.sum())
