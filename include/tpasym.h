@@ -332,9 +332,13 @@ int tp_coords(const tp_events *ev, const int32_t *masks, int32_t ncoord, double 
  * distance as a dot product of (coordinates - centre, squared norm) vectors
  * split into float16 terms on the matrix cores (centre: mean of the first 256
  * events; rounding grows with the squared distance of the events from it, in
- * units of sigma, and is of random sign), then the hardware exp2.  An event
- * farther than ~37 sigma from the centre (scaled squared distance > 1024)
- * makes the sums NaN.  psi enters the matrix cores again as two float16 terms (truncation
+ * units of sigma, and is of random sign), then the hardware exp2.  A range
+ * check runs first: if any event lies farther than ~37 sigma from the centre
+ * (scaled squared distance > 1024) or is not finite, the launch instead forms
+ * the distances of every chunk of pairs that holds such an event as direct
+ * float32 differences of the coordinates (slower, accurate at any distance).
+ * Calls on one stream share a two-word device flag of the library.
+ * psi enters the matrix cores again as two float16 terms (truncation
  * of psi * 2^14 and of the remainder: together within 2^-20 of psi,
  * relative); the 0/1 columns are exact in float16, products are accumulated
  * in float32 over 1024 j and then in float64.  Sums are accurate to ~1e-5

@@ -19,6 +19,7 @@ struct EParams {
     float yscale;             // sqrt(log2(e) / (2 sigma^2)): psi = 2^-(yscale d)^2
     const uint8_t *G;
     double *sums;
+    uint32_t *flag;           // device [2]: range flag, finished workgroups (zero between launches)
 };
 
 // Coordinate launch: invariant masses of ncoord slot masks per event.

@@ -26,7 +26,15 @@
 // about 2^-22 (2 |v_i|^2 + 2 |v_j|^2) plus the float32 accumulation; centring
 // keeps |v|^2 small (a few units for invariant masses at sigma ~ 0.3 GeV, ~100
 // at 0.05 GeV), and the errors are of random sign, so sums over many pairs
-// keep ~1e-8.  Events with |v|^2 > VMAX2 make the sums NaN.
+// keep ~1e-8.  An event with |v|^2 > VMAX2 (or a non-finite one) is outside
+// that range.  A range check over all events runs first and sets a device
+// flag; the kernel is launched in two instantiations, of which only one does
+// the work: without the flag the matrix-core form above, with it the SAFE form,
+// in which every chunk of pairs that holds such an event as a row or as a
+// column forms its distances as direct float32 differences of the raw
+// coordinates, (y_i - y_j) yscale, squared and summed on the vector ALU
+// (accurate at any distance from the centre), the matrix-core operands of
+// those events being finite placeholders.
 // V = Psi G is then a dense contraction over j in half precision with float32
 // accumulation (v_mfma_f32_32x32x16_f16): psi * 2^14 is split into two float16
 // terms hi = rtz(psi), lo = rtz(psi - hi): the difference is exact in float32
@@ -64,13 +72,13 @@ constexpr int FL = 8;         // chunks per float32 -> float64 reduction
 constexpr int GPAD = 8;       // float16 padding per staged column (spreads LDS banks)
 constexpr int XS = 40;        // float16 slots per staged j vector: 32 used, 8 padding (spreads LDS banks)
 constexpr float PSI_LOG2 = 14.0f;             // psi is formed scaled by 2^14
-// Largest |v|^2 (squared scaled distance from the centre) of an event: the
-// distance rounding grows as 2^-22 |v|^2, and float16 holds |v|^2 only below
-// 65504.  An event beyond it gets a NaN norm, which makes every sum NaN.
+// Largest |v|^2 (squared scaled distance from the centre) of an event whose
+// distances go through the matrix cores: their rounding grows as 2^-22 |v|^2,
+// and float16 holds |v|^2 only below 65504.
 constexpr float VMAX2 = 1024.0f;
 constexpr double PSI_UNSCALE = 1.0 / 16384.0;
 
-template <int NT>
+template <int NT, bool SAFE>
 struct Smem {
     static constexpr int C = 32 * NT;
     uint16_t xh[JC][XS];                // chunk j distance operands, float16 slots (see slot())
@@ -80,12 +88,21 @@ struct Smem {
     uint8_t gi[ROWS * C];               // columns of this block's rows, [i][c]
     float rw[ROWS][8];                  // per row: weights G[i][q] (0..2), (Psi_upper G)[i][q] (4..6)
     double red[C][1 + MAXR];            // workgroup totals
+    // SAFE: raw coordinates of the block's rows and of the chunk's events (direct distances)
+    float yr[SAFE ? ROWS : 1][MAXD + 1];
+    float yc[SAFE ? JC : 1][MAXD];
+};
+
+// The centre's scratch of the range check (same fields as Smem).
+struct CentreSmem {
+    float cw[4][MAXD];
+    float cen[MAXD];
 };
 
 // Centre c of the scaled coordinates: the mean of the first min(n, 256)
 // events, formed in a fixed order so that every workgroup gets the same bits.
-template <int NT>
-__device__ __forceinline__ void centre(const EParams &p, Smem<NT> &sm)
+template <class SM>
+__device__ __forceinline__ void centre(const EParams &p, SM &sm)
 {
     const int tid = threadIdx.x;
     const int64_t m = p.n < 256 ? p.n : 256;
@@ -138,8 +155,8 @@ __device__ __forceinline__ void split16(const float (&x)[KA], uint16_t (&hi)[KA]
 // |y_i - c|^2) (scaled coordinates, so psi = 2^-(scaled distance)^2):
 // x_i . x_j = |y_i - y_j|^2 for the chunk vectors x_j.  Lane half h holds
 // slots 16 m + 8 h .. + 7 of the row pattern for the two distance steps m.
-template <int NT, int NS>
-__device__ __forceinline__ void setup_rows(const EParams &p, Smem<NT> &sm, int64_t ib, u32x4 (&xi)[2])
+template <int NT, int NS, bool SAFE>
+__device__ __forceinline__ bool setup_rows(const EParams &p, Smem<NT, SAFE> &sm, int64_t ib, u32x4 (&xi)[2])
 {
     constexpr int C = 32 * NT;
     constexpr int KA = 2 * NS;
@@ -165,13 +182,24 @@ __device__ __forceinline__ void setup_rows(const EParams &p, Smem<NT> &sm, int64
     float nrm = 0.0f;
 #pragma unroll
     for (int k = 0; k < KA; ++k) x[k] = 0.0f;
+    const int rl = (tid >> 6) * 32 + (tid & 31);
 #pragma unroll
     for (int d = 0; d < KA - 2; ++d) {
-        const float v = (d < p.D && i < p.n) ? p.Y[d * p.ldY + i] * p.yscale - sm.cen[d] : 0.0f;
+        const float y = (d < p.D && i < p.n) ? p.Y[d * p.ldY + i] : 0.0f;
+        const float v = (d < p.D && i < p.n) ? y * p.yscale - sm.cen[d] : 0.0f;
         nrm = fmaf(v, v, nrm);
         if (d < p.D) x[d] = -2.0f * v;
+        if constexpr (SAFE)
+            if (h == 0 && d < p.D) sm.yr[rl][d] = y;
     }
-    if (!(nrm <= VMAX2)) nrm = __builtin_nanf("");
+    // outside the matrix-core range (only in the SAFE form, by the range check):
+    // finite placeholders; the chunks of this row block take the direct distances
+    const bool far = !(nrm <= VMAX2);
+    if (SAFE && far) {
+        nrm = 0.0f;
+#pragma unroll
+        for (int k = 0; k < KA; ++k) x[k] = 0.0f;
+    }
 #pragma unroll
     for (int k = 0; k < KA; ++k) {
         if (k == p.D) x[k] = 1.0f;
@@ -186,6 +214,8 @@ __device__ __forceinline__ void setup_rows(const EParams &p, Smem<NT> &sm, int64
             const int s0 = 16 * m + 8 * h + 2 * w;
             xi[m][w] = (uint32_t)slot<KA, false>(hi, lo, s0) | ((uint32_t)slot<KA, false>(hi, lo, s0 + 1) << 16);
         }
+    if constexpr (SAFE) return __syncthreads_or(far) != 0;
+    return false;
 }
 
 // Position of local j in a staged column: bits 2 and 3 swapped, the order in
@@ -229,12 +259,13 @@ __device__ __forceinline__ void load_chunk(const EParams &p, int64_t j0, Pending
     }
 }
 
-template <int NT, int KA>
-__device__ __forceinline__ void store_chunk(const EParams &p, Smem<NT> &sm, int64_t j0, const Pending<KA> &pd)
+template <int NT, int KA, bool SAFE>
+__device__ __forceinline__ bool store_chunk(const EParams &p, Smem<NT, SAFE> &sm, int64_t j0, const Pending<KA> &pd)
 {
     constexpr int C = 32 * NT;
     constexpr int ITEMS = (JC / 4) * (C / 16);
     const int tid = threadIdx.x;
+    bool far = false;
     if (tid < JC) {
         const bool real = j0 + tid < p.n;   // padding events sit at the centre
         float x[KA];
@@ -246,8 +277,15 @@ __device__ __forceinline__ void store_chunk(const EParams &p, Smem<NT> &sm, int6
             const float v = (d < p.D && real) ? pd.y[d] * p.yscale - sm.cen[d] : 0.0f;
             nrm = fmaf(v, v, nrm);
             if (d < p.D) x[d] = v;
+            if constexpr (SAFE)
+                if (d < p.D) sm.yc[tid][d] = real ? pd.y[d] : 0.0f;
         }
-        if (!(nrm <= VMAX2)) nrm = __builtin_nanf("");
+        far = !(nrm <= VMAX2);
+        if (SAFE && far) {
+            nrm = 0.0f;
+#pragma unroll
+            for (int k = 0; k < KA; ++k) x[k] = 0.0f;
+        }
 #pragma unroll
         for (int k = 0; k < KA; ++k) {
             if (k == p.D) x[k] = nrm;
@@ -280,6 +318,7 @@ __device__ __forceinline__ void store_chunk(const EParams &p, Smem<NT> &sm, int6
             *reinterpret_cast<u32x2 *>(&sm.gs[16 * cg + q][swap23(jq)]) = u32x2{ (uint32_t)__umul24(x01, 0x3C00u), (uint32_t)__umul24(x23, 0x3C00u) };
         }
     }
+    return far;
 }
 
 // psi products of one staged chunk into the float32 tiles, 32 j per step.
@@ -293,8 +332,12 @@ __device__ __forceinline__ void store_chunk(const EParams &p, Smem<NT> &sm, int6
 // which is k with bits 2 and 3 swapped, the order in which the columns are
 // staged.  MASK keeps only j > rel (rel = i - j0), needed only in the chunk
 // that holds the diagonal.
-template <int NT, bool MASK>
-__device__ __forceinline__ void chunk_products(const Smem<NT> &sm, const u32x4 (&xi)[2], int rel, f32x16 (&acc)[NT])
+// DIRECT (SAFE form only): the distances of the chunk as direct float32
+// differences of the raw coordinates instead, |(y_i - y_j) yscale|^2 - 14 for
+// the same lane layout.
+template <int NT, bool MASK, bool SAFE, bool DIRECT>
+__device__ __forceinline__ void chunk_products(const Smem<NT, SAFE> &sm, const u32x4 (&xi)[2], int rel,
+                                               f32x16 (&acc)[NT], int D, float yscale)
 {
     const int lane = threadIdx.x & 63;
     const int h = lane >> 5;
@@ -302,10 +345,24 @@ __device__ __forceinline__ void chunk_products(const Smem<NT> &sm, const u32x4 (
 #pragma unroll 1
     for (int jb = 0; jb < JC; jb += 2 * KS) {
         f32x16 dd = f32x16{};
+        if constexpr (DIRECT) {
+            const int row = (threadIdx.x >> 6) * 32 + col;
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-            const f16x8 A = *reinterpret_cast<const f16x8 *>(&sm.xh[jb + col][16 * m + 8 * h]);
-            dd = __builtin_amdgcn_mfma_f32_32x32x16_f16(A, __builtin_bit_cast(f16x8, xi[m]), dd, 0, 0, 0);
+            for (int r = 0; r < 16; ++r) {
+                const int j = jb + 8 * (r >> 2) + 4 * h + (r & 3);
+                float d2 = 0.0f;
+                for (int d = 0; d < D; ++d) {
+                    const float t = (sm.yr[row][d] - sm.yc[j][d]) * yscale;
+                    d2 = fmaf(t, t, d2);
+                }
+                dd[r] = d2 - PSI_LOG2;
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                const f16x8 A = *reinterpret_cast<const f16x8 *>(&sm.xh[jb + col][16 * m + 8 * h]);
+                dd = __builtin_amdgcn_mfma_f32_32x32x16_f16(A, __builtin_bit_cast(f16x8, xi[m]), dd, 0, 0, 0);
+            }
         }
         u32x4 ah[2], al[2];
 #pragma unroll
@@ -347,8 +404,9 @@ __device__ __forceinline__ void chunk_products(const Smem<NT> &sm, const u32x4 (
 // wave's 32.  The leading R columns are the row weights; their values
 // (Psi_upper w_q)_i go through LDS so that every column can take the
 // transposed term sum_i G_ic (Psi_upper w_q)_i.
-template <int NT, int RR>
-__device__ __forceinline__ void flush(const EParams &p, Smem<NT> &sm, f32x16 (&acc)[NT], double (&part)[NT][1 + RR])
+template <int NT, int RR, bool SAFE>
+__device__ __forceinline__ void flush(const EParams &p, Smem<NT, SAFE> &sm, f32x16 (&acc)[NT],
+                                      double (&part)[NT][1 + RR])
 {
     constexpr int C = 32 * NT;
     const int tid = threadIdx.x;
@@ -394,11 +452,14 @@ __device__ __forceinline__ void flush(const EParams &p, Smem<NT> &sm, f32x16 (&a
 // equal contiguous pieces, so the launch has enough equal-sized workgroups to
 // keep every compute unit busy to the end.
 // RR: row-weight columns the reduction carries (RR covers R <= RR).
-template <int NT, int NS, int RR>
+template <int NT, int NS, int RR, bool SAFE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void tp_pairsum_kernel(const EParams p, const int K)
 {
     constexpr int C = 32 * NT;
-    __shared__ __align__(16) Smem<NT> sm;
+    // the range check's flag selects the one instantiation that works
+    const bool flagged = __atomic_load_n(p.flag, __ATOMIC_RELAXED) != 0u;
+    if (flagged != SAFE) return;
+    __shared__ __align__(16) Smem<NT, SAFE> sm;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -422,7 +483,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void t
     const int64_t L2 = b2 > b1 ? (p.n - b2 * ROWS + JC - 1) / JC : 0;
     const int64_t L = L1 + L2;
     const int64_t v0 = k * L / K, v1 = (k + 1) * L / K;
-    centre<NT>(p, sm);
+    centre(p, sm);
     u32x4 xi[2];
     int64_t cur = -1;
     int since = 0;
@@ -430,23 +491,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void t
     auto chunk_j0 = [&](int64_t v) { return v < L1 ? b1 * ROWS + v * JC : b2 * ROWS + (v - L1) * JC; };
     Pending<2 * NS> pd;
     if (v0 < v1) load_chunk<NT, 2 * NS>(p, chunk_j0(v0), pd);
+    bool rows_far = false;
     for (int64_t v = v0; v < v1; ++v) {
         const int64_t blk = v < L1 ? b1 : b2;
         const int64_t c0 = v < L1 ? v : v - L1;      // chunk within the block's row
         const int64_t j0 = chunk_j0(v);
         if (blk != cur) {
-            setup_rows<NT, NS>(p, sm, blk * ROWS, xi);
+            rows_far = setup_rows<NT, NS, SAFE>(p, sm, blk * ROWS, xi);
             cur = blk;
         }
         __syncthreads();
-        store_chunk<NT, 2 * NS>(p, sm, j0, pd);
-        __syncthreads();
+        const bool cfar = store_chunk<NT, 2 * NS, SAFE>(p, sm, j0, pd);
+        bool far = false;
+        if constexpr (SAFE) far = __syncthreads_or(cfar) != 0 || rows_far;
+        else __syncthreads();
         if (v + 1 < v1) load_chunk<NT, 2 * NS>(p, chunk_j0(v + 1), pd);
-        if (c0 == 0) chunk_products<NT, true>(sm, xi, wave * 32 + col, acc);
-        else chunk_products<NT, false>(sm, xi, 0, acc);
+        if (SAFE && far) {    // uniform over the workgroup
+            if (c0 == 0) chunk_products<NT, true, SAFE, SAFE>(sm, xi, wave * 32 + col, acc, p.D, p.yscale);
+            else chunk_products<NT, false, SAFE, SAFE>(sm, xi, 0, acc, p.D, p.yscale);
+        } else {
+            if (c0 == 0) chunk_products<NT, true, SAFE, false>(sm, xi, wave * 32 + col, acc, p.D, p.yscale);
+            else chunk_products<NT, false, SAFE, false>(sm, xi, 0, acc, p.D, p.yscale);
+        }
         const bool block_ends = v + 1 == v1 || v + 1 == L1;
         if (++since == FL || block_ends) {
-            flush<NT, RR>(p, sm, acc, part);
+            flush<NT, RR, SAFE>(p, sm, acc, part);
             since = 0;
         }
     }
@@ -466,6 +535,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void t
             const int c = e / (1 + R), q = e % (1 + R);
             if (c < p.C) atomicAdd(&p.sums[(int64_t)c * (1 + R) + q], sm.red[c][q] * PSI_UNSCALE);
         }
+    if constexpr (SAFE) {
+        // the last workgroup clears the flag and the count for the next launch
+        __shared__ bool last;
+        __syncthreads();
+        if (tid == 0) {
+            __threadfence();
+            last = atomicAdd(p.flag + 1, 1u) == gridDim.x - 1;
+        }
+        __syncthreads();
+        if (last && tid == 0) {
+            p.flag[0] = 0u;
+            p.flag[1] = 0u;
+            __threadfence();
+        }
+    }
+}
+
+// Range check: sets p.flag[0] when any event lies outside the matrix-core
+// range of the centre (|v|^2 > VMAX2, or not finite), with the same centre
+// and the same arithmetic as the pair-sum kernels.
+__global__ __launch_bounds__(256) void tp_range_kernel(const EParams p)
+{
+    __shared__ CentreSmem sm;
+    centre(p, sm);
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= p.n) return;
+    float nrm = 0.0f;
+    for (int d = 0; d < p.D; ++d) {
+        const float v = p.Y[d * p.ldY + i] * p.yscale - sm.cen[d];
+        nrm = fmaf(v, v, nrm);
+    }
+    if (!(nrm <= VMAX2)) atomicOr(p.flag, 1u);
 }
 
 template <int NT, int NS, int RR>
@@ -480,7 +581,9 @@ void launch_ntd(const EParams &p, hipStream_t st)
     int64_t K = (16384 + pairs - 1) / pairs;
     K = K > chunks / 2 ? chunks / 2 : K;
     K = K < 1 ? 1 : K;
-    hipLaunchKernelGGL((tp_pairsum_kernel<NT, NS, RR>), dim3((unsigned)(pairs * K)), dim3(256), 0, st, p, (int)K);
+    // one of the two instantiations works (the range check's flag), the other exits
+    hipLaunchKernelGGL((tp_pairsum_kernel<NT, NS, RR, false>), dim3((unsigned)(pairs * K)), dim3(256), 0, st, p, (int)K);
+    hipLaunchKernelGGL((tp_pairsum_kernel<NT, NS, RR, true>), dim3((unsigned)(pairs * K)), dim3(256), 0, st, p, (int)K);
 }
 
 template <int NT, int RR>
@@ -577,6 +680,7 @@ __global__ void tp_coords_kernel(CParams c)
 
 hipError_t launch_pairsums(const EParams &p, hipStream_t st)
 {
+    hipLaunchKernelGGL(tp_range_kernel, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, st, p);
     const int nt = p.C / 32;
     switch (nt) {
     case 1: launch_nt<1>(p, st); break;

@@ -143,6 +143,7 @@ struct Device {
     std::map<std::string, tp_tuning> tuned;
     uint64_t *scratch_counts = nullptr;   // autotune sink
     size_t scratch_words = 0;
+    std::map<hipStream_t, uint32_t *> eflag;   // pair sums per stream: range flag, workgroup count
 };
 
 std::mutex g_mu;
@@ -1106,6 +1107,7 @@ int tp_autotune(const tp_sample *samples, int32_t nsamples, int32_t precision, v
         Device &d = device(dev);
         if (d.scratch_words < words) {
             if (d.scratch_counts) hipFree(d.scratch_counts);
+        for (auto &f : d.eflag) hipFree(f.second);
             if (hipMalloc(&d.scratch_counts, words * 8) != hipSuccess) {
                 d.scratch_counts = nullptr;
                 d.scratch_words = 0;
@@ -1378,6 +1380,7 @@ int tp_release(void)
             hipFree(g.second.ws.buf);
         }
         if (d.scratch_counts) hipFree(d.scratch_counts);
+        for (auto &f : d.eflag) hipFree(f.second);
     }
     g_dev.clear();
     return TP_OK;
@@ -1457,6 +1460,23 @@ int tp_pairsums(const float *coords, int32_t dims, int64_t ld, int64_t n, double
     p.yscale = (float)std::sqrt(1.4426950408889634 / (2.0 * sigma * sigma));
     p.G = cols;
     p.sums = sums;
+    {
+        int dev = 0;
+        TP_HIP(hipGetDevice(&dev));
+        std::lock_guard<std::mutex> lk(g_mu);
+        Device &d = device(dev);
+        const hipStream_t st = static_cast<hipStream_t>(stream);
+        uint32_t *&f = d.eflag[st];
+        if (!f) {
+            // zero once; each launch that sets the flag clears it when done
+            if (hipMalloc(&f, 2 * sizeof(uint32_t)) != hipSuccess) {
+                d.eflag.erase(st);
+                return fail(TP_ENOMEM, "flag allocation failed");
+            }
+            TP_HIP(hipMemset(f, 0, 2 * sizeof(uint32_t)));
+        }
+        p.flag = f;
+    }
     TP_HIP(tpe::launch_pairsums(p, static_cast<hipStream_t>(stream)));
     return TP_OK;
 }

@@ -304,28 +304,62 @@ def test_raw_pair_sums_sigma_range(tp, sigma):
         assert np.all(np.abs(S[:, 1 + q] - wq) <= 1e-5 * wq + 1e-9), q
 
 
-def test_pair_sums_far_event_gives_nan(tp):
-    """An event whose scaled squared distance from the centre (the mean of the first 256
-    events) exceeds 1024, i.e. ~37 sigma away, is outside the range in which the matrix-core
-    distances are accurate: the sums come out NaN instead of silently imprecise.  The same
-    coordinates without that event give finite sums that match the dense float64 psi."""
-    n, C, sigma = 300, 32, 0.3
-    rng = np.random.default_rng(31)
-    Yh = rng.normal(1.0, 0.3, size=(2, n)).astype(np.float32)
-    G = (rng.uniform(size=(n, C)) < 0.5).astype(np.uint8)
-    Gd = torch.from_numpy(G).cuda()
-    ok = tp.pairsums(torch.from_numpy(Yh).cuda(), Gd, sigma, nrow=1)
-    Yfar = Yh.copy()
-    Yfar[:, n - 1] = 20.0                               # ~ (19 GeV / 0.3 GeV) * 0.85 = 54 scaled units
-    bad = tp.pairsums(torch.from_numpy(Yfar).cuda(), Gd, sigma, nrow=1)
+def _dense_check(tp, Yh, G, sigma, nrow, tol=1e-5):
+    """Pair sums of float32 coordinates Yh [D][n] against the dense float64 psi matrix."""
+    sums = tp.pairsums(torch.from_numpy(np.ascontiguousarray(Yh)).cuda(), torch.from_numpy(G).cuda(), sigma, nrow=nrow)
     torch.cuda.synchronize()
-    assert np.all(np.isnan(bad.cpu().numpy()))
-    S = ok.cpu().numpy()
+    S = sums.cpu().numpy()
+    assert np.all(np.isfinite(S))
     Psi = energy.psi_block(Yh.astype(np.float64), Yh.astype(np.float64), sigma)
     np.fill_diagonal(Psi, 0.0)
     Gf = G.astype(np.float64)
-    want0 = np.einsum("ic,ic->c", Gf, Psi @ Gf)
-    assert np.all(np.abs(S[:, 0] - want0) <= 1e-5 * want0 + 1e-9)
+    V = Psi @ Gf
+    want0 = np.einsum("ic,ic->c", Gf, V)
+    assert np.all(np.abs(S[:, 0] - want0) <= tol * want0 + 1e-9)
+    for q in range(nrow):
+        wq = Gf[:, q] @ V
+        assert np.all(np.abs(S[:, 1 + q] - wq) <= tol * wq + 1e-9), q
+    return S
+
+
+def test_pair_sums_far_events(tp):
+    """Events far from the centre (the mean of the first 256 events) in sigma units --
+    beyond the range in which the matrix-core distances are accurate -- take direct
+    float32 differences in every chunk of pairs that holds them: the sums match the dense
+    float64 psi.  Far events are placed as rows of the first block, as columns of a late
+    chunk, and as two far events close to each other (their pair's psi is large)."""
+    n, C, sigma = 1300, 32, 0.3
+    rng = np.random.default_rng(31)
+    Yh = rng.normal(1.0, 0.3, size=(2, n)).astype(np.float32)
+    G = (rng.uniform(size=(n, C)) < 0.5).astype(np.uint8)
+    Yfar = Yh.copy()
+    Yfar[:, n - 1] = 20.0                       # ~ (19 GeV / 0.3 GeV) * 0.85 = 54 scaled units
+    Yfar[:, n - 2] = 20.05                      # close to the previous one: psi ~ 0.97
+    Yfar[:, 5] = -40.0                          # a row of the first block
+    Yfar[:, 700] = [1e4, -3e3]                  # very far: every psi with it underflows
+    _dense_check(tp, Yfar, G, sigma, 1)
+    _dense_check(tp, Yfar, G, sigma, 2)
+
+
+@pytest.mark.parametrize("sigma,far_min", [(0.15, 0.0), (0.04, 0.3)])
+def test_pair_sums_lambda_b_masses(tp, sigma, far_min):
+    """Lambda_b -> p K- pi+ pi- invariant masses (spreads of several GeV) against the dense
+    float64 psi at sigma = 0.15 GeV and at sigma = 0.04 GeV, where about half of the events lie
+    beyond the matrix-core range around the first 256 events' mean."""
+    ch = synth.CHANNELS["Lb_pKpipi"]
+    s = synth.generate(ch, 2051, 35)
+    masks = [0b0011, 0b1001, 0b0110, 0b1100, 0b0111]
+    Yg = tp.coords(tp.DeviceSample.from_sample(s), masks, 1e-3)
+    comps, _ = s.numpy()
+    Yo = energy.invariant_masses(comps, masks) * 1e-3
+    yscale = np.sqrt(np.log2(np.e) / (2 * sigma ** 2))
+    far = ((Yo - Yo[:, :256].mean(axis=1, keepdims=True)) ** 2).sum(axis=0) * yscale ** 2 > 1024
+    print(f"[energy] Lambda_b masses at sigma {sigma}: {far.mean():.2f} of the events beyond the matrix-core "
+          f"range", flush=True)
+    assert far.mean() >= far_min
+    rng = np.random.default_rng(36)
+    G = (rng.uniform(size=(2051, 64)) < rng.uniform(0.1, 0.9, size=64)).astype(np.uint8)
+    _dense_check(tp, Yg.cpu().numpy(), G, sigma, 2)
 
 
 ALL_MASKS = [0b0011, 0b0101, 0b0110, 0b1001, 0b1010, 0b1100, 0b0111, 0b1011, 0b1101, 0b1110, 0b1111]
