@@ -1107,7 +1107,6 @@ int tp_autotune(const tp_sample *samples, int32_t nsamples, int32_t precision, v
         Device &d = device(dev);
         if (d.scratch_words < words) {
             if (d.scratch_counts) hipFree(d.scratch_counts);
-        for (auto &f : d.eflag) hipFree(f.second);
             if (hipMalloc(&d.scratch_counts, words * 8) != hipSuccess) {
                 d.scratch_counts = nullptr;
                 d.scratch_words = 0;

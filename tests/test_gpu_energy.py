@@ -341,6 +341,28 @@ def test_pair_sums_far_events(tp):
     _dense_check(tp, Yfar, G, sigma, 2)
 
 
+def test_pair_sums_after_autotune(tp):
+    """The per-stream range flag of the pair sums survives autotuning: pair sums with far
+    events (the flag is set, then cleared by the safe form), two autotunes whose counter
+    scratch grows (histograms larger than any other test's), pair sums again on the same
+    stream; both calls match the dense float64 psi.  (The autotuner once freed the flags
+    when it grew its scratch, leaving the pair sums a freed flag.)"""
+    n, C, sigma = 1300, 32, 0.3
+    rng = np.random.default_rng(41)
+    Yh = rng.normal(1.0, 0.3, size=(2, n)).astype(np.float32)
+    Yh[:, 3] = 30.0
+    G = (rng.uniform(size=(n, C)) < 0.5).astype(np.uint8)
+    _dense_check(tp, Yh, G, sigma, 1)
+    ch, s = sample(4099, 42)
+    ds = tp.DeviceSample.from_sample(s)
+    for nb in (40, 50):
+        bn = tp.Binning([synth.abscos_axis(0, nb), synth.mass_axis((0, 1), 980.0, 1600.0, nb)])
+        counts, stats = tp.new_counts(bn)
+        tp.Batch([(ds, tp.channel(ch.triple, ch.planes), bn, counts, stats)]).autotune(tp.TP_PREC_F64)
+    _dense_check(tp, Yh, G, sigma, 1)
+    _dense_check(tp, Yh, G, sigma, 2)
+
+
 @pytest.mark.parametrize("sigma,far_min", [(0.15, 0.0), (0.04, 0.3)])
 def test_pair_sums_lambda_b_masses(tp, sigma, far_min):
     """Lambda_b -> p K- pi+ pi- invariant masses (spreads of several GeV) against the dense
