@@ -141,10 +141,19 @@ struct Device {
     std::list<uint64_t> lru;
     std::unordered_map<uint64_t, GraphEntry> graphs;
     std::map<std::string, tp_tuning> tuned;
+    bool tune_loaded = false;             // TP_TUNE_CACHE read into ``tuned``
     uint64_t *scratch_counts = nullptr;   // autotune sink
     size_t scratch_words = 0;
     std::map<hipStream_t, uint32_t *> eflag;   // pair sums per stream: range flag, workgroup count
+    // scheme groups of one launch run on parallel branches: the caller's
+    // stream and up to NSIDE side streams (default priority), forked from and
+    // joined back into the caller's stream by events
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> join;
+    hipEvent_t fork = nullptr;
 };
+
+constexpr int NSIDE = 3;
 
 std::mutex g_mu;
 std::map<int, Device> g_dev;
@@ -615,6 +624,31 @@ void defaults(tp_tuning &t)
     if (t.unroll != 1 && t.unroll != 2 && t.unroll != 4) t.unroll = 1;
 }
 
+// The device's side streams and fork/join events, created on first use.
+int side_streams(Device &d)
+{
+    if (d.fork) return TP_OK;
+    hipError_t e = hipSuccess;
+    for (int l = 0; l < NSIDE && e == hipSuccess; ++l) {
+        hipStream_t s2 = nullptr;
+        hipEvent_t e2 = nullptr;
+        e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
+        if (e == hipSuccess) d.side.push_back(s2);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&e2, hipEventDisableTiming);
+        if (e == hipSuccess) d.join.push_back(e2);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&d.fork, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        for (hipStream_t s2 : d.side) hipStreamDestroy(s2);
+        for (hipEvent_t e2 : d.join) hipEventDestroy(e2);
+        d.side.clear();
+        d.join.clear();
+        d.fork = nullptr;
+        return fail(TP_EHIP, std::string("side streams: ") + hipGetErrorString(e));
+    }
+    return TP_OK;
+}
+
 // One pass launch over the samples of group g with launch shape ``tu``;
 // ``kp`` carries the plan's tables and the deferral workspace.
 int launch_group(int cus, const Group &g, tp_tuning tu, int dtype, int prec, int mode, KParams kp, hipStream_t st)
@@ -677,13 +711,42 @@ int launch_plan(Device &d, const Plan &p, const std::vector<tp_tuning> &gtu, int
     kp.xdone = ws.xdone;
     kp.xcap = (uint32_t)ws.cap;
     kp.mode = mode;
+    // Several scheme groups run as parallel branches (group k on stream
+    // k mod (NSIDE + 1), stream 0 being the caller's): their launches overlap,
+    // so one kernel's last workgroups share the chip with the next kernel's
+    // first, and memory-bound and issue-bound schemes share the compute units.
+    // The exact tier waits for all of them.  (Under graph capture the side
+    // streams join the capture through the fork event and leave it through
+    // the joins.)
+    int ngroups = 0;
+    for (const Group &g : p.groups) ngroups += g.vend > g.vbeg;
+    const bool fork = only < 0 && ngroups > 1;
+    bool joined[NSIDE] = {};
+    if (fork) {
+        int rc = side_streams(d);
+        if (rc) return rc;
+        TP_HIP(hipEventRecord(d.fork, st));
+    }
+    int k = 0;
     for (size_t gi = 0; gi < p.groups.size(); ++gi) {
         if (only >= 0 && (size_t)only != gi) continue;
         const Group &g = p.groups[gi];
         const int64_t nv = g.vend - g.vbeg;
         if (nv <= 0) continue;
-        const int rc = launch_group(d.cus, g, gtu[gi], p.dtype, prec, mode, kp, st);
+        const int lane = fork ? k++ % (NSIDE + 1) : 0;
+        hipStream_t gs = st;
+        if (lane > 0) {
+            gs = d.side[lane - 1];
+            if (!joined[lane - 1]) TP_HIP(hipStreamWaitEvent(gs, d.fork, 0));
+            joined[lane - 1] = true;
+        }
+        const int rc = launch_group(d.cus, g, gtu[gi], p.dtype, prec, mode, kp, gs);
         if (rc) return rc;
+    }
+    for (int l = 0; l < NSIDE; ++l) {
+        if (!joined[l]) continue;
+        TP_HIP(hipEventRecord(d.join[l], d.side[l]));
+        TP_HIP(hipStreamWaitEvent(st, d.join[l], 0));
     }
     if (timed) {
         TP_HIP(hipEventRecord(e1, st));
@@ -739,18 +802,21 @@ std::string tune_key(const std::vector<Req> &rq, int prec)
 
 void load_tune_file(Device &d)
 {
-    static bool loaded = false;
-    if (loaded) return;
-    loaded = true;
+    if (d.tune_loaded) return;
+    d.tune_loaded = true;
     const char *fn = std::getenv("TP_TUNE_CACHE");
     if (!fn) return;
     FILE *f = std::fopen(fn, "r");
     if (!f) return;
     char key[200];
     tp_tuning t;
-    while (std::fscanf(f, " \"%199[^\"]\": [%d, %d, %d, %d]%*[,}\n ]", key, &t.block, &t.wg_per_cu,
-                       &t.lds_copies, &t.unroll) == 5)
-        d.tuned[key] = t;
+    // {"key": [block, wg_per_cu, lds_copies, unroll], ...}: the opening brace,
+    // then one entry per line
+    if (std::fscanf(f, " {") == 0) {
+        while (std::fscanf(f, " \"%199[^\"]\": [%d, %d, %d, %d]%*[,}\n ]", key, &t.block, &t.wg_per_cu,
+                           &t.lds_copies, &t.unroll) == 5)
+            d.tuned[key] = t;
+    }
     std::fclose(f);
 }
 
@@ -1380,6 +1446,9 @@ int tp_release(void)
         }
         if (d.scratch_counts) hipFree(d.scratch_counts);
         for (auto &f : d.eflag) hipFree(f.second);
+        for (hipStream_t s2 : d.side) hipStreamDestroy(s2);
+        for (hipEvent_t e2 : d.join) hipEventDestroy(e2);
+        if (d.fork) hipEventDestroy(d.fork);
     }
     g_dev.clear();
     return TP_OK;

@@ -344,7 +344,7 @@ def test_pair_sums_far_events(tp):
 def test_pair_sums_after_autotune(tp):
     """The per-stream range flag of the pair sums survives autotuning: pair sums with far
     events (the flag is set, then cleared by the safe form), two autotunes whose counter
-    scratch grows (histograms larger than any other test's), pair sums again on the same
+    scratch grows (batches of 8 and 16 samples of 1024 bins), pair sums again on the same
     stream; both calls match the dense float64 psi.  (The autotuner once freed the flags
     when it grew its scratch, leaving the pair sums a freed flag.)"""
     n, C, sigma = 1300, 32, 0.3
@@ -355,10 +355,10 @@ def test_pair_sums_after_autotune(tp):
     _dense_check(tp, Yh, G, sigma, 1)
     ch, s = sample(4099, 42)
     ds = tp.DeviceSample.from_sample(s)
-    for nb in (40, 50):
-        bn = tp.Binning([synth.abscos_axis(0, nb), synth.mass_axis((0, 1), 980.0, 1600.0, nb)])
-        counts, stats = tp.new_counts(bn)
-        tp.Batch([(ds, tp.channel(ch.triple, ch.planes), bn, counts, stats)]).autotune(tp.TP_PREC_F64)
+    bn = tp.Binning([synth.abscos_axis(0, 32), synth.mass_axis((0, 1), 980.0, 1600.0, 32)])
+    for copies in (8, 16):
+        items = [(ds, tp.channel(ch.triple, ch.planes), bn, *tp.new_counts(bn)) for _ in range(copies)]
+        tp.Batch(items).autotune(tp.TP_PREC_F64)
     _dense_check(tp, Yh, G, sigma, 1)
     _dense_check(tp, Yh, G, sigma, 2)
 
