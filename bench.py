@@ -368,15 +368,18 @@ def scp_report(items, reps):
     return {"columns": ["chi2_P_even", "p_P_even", "chi2_P_odd", "p_P_odd", "ndf"], "per_sample": rows}
 
 
-def d0_leg(dev, steps, warmup):
-    """The largest single-sample workload: 5e8 D0 -> K+ K- pi+ pi- events, 32 x 32
-    bins in (m(K+K-), m(pi+pi-)), float32 storage: the float32 sign tier with the
-    float64 recheck is the path that runs here (no plane angle is binned)."""
+def single_leg(dev, workload, steps, warmup, chunk=0):
+    """One large single-sample workload, resident in HBM, timed as a graphed
+    pass (float32 storage, TP_PREC_F32_RECHECK requested: the float32 sign tier
+    runs where no plane angle is binned, the first pass where one is).  With
+    ``chunk`` > 0 the same events are also passed as consecutive chunks of that
+    many events (one tp_bin call each, into the same counters), as a caller
+    streaming them would, and the counts must be the same."""
     import numpy as np
     import torch
     from paper_1612_04705_amd import synth, tpasym
     t0 = time.time()
-    spec = synth.workload_specs("d0_kkpipi_5e8_m32x32")[0]
+    spec = synth.workload_specs(workload)[0]
     smp = synth.make_sample(spec, device=dev)
     ds = tpasym.DeviceSample([smp.comps[a][b] for a in range(4) for b in range(4)], smp.tag)
     del smp
@@ -385,18 +388,19 @@ def d0_leg(dev, steps, warmup):
     ch = tpasym.channel(spec.channel.triple, spec.channel.planes)
     counts, stats = tpasym.new_counts(bn, dev)
     b = tpasym.Batch([(ds, ch, bn, counts, stats)])
+    prec = tpasym.TP_PREC_F32_RECHECK
     torch.cuda.synchronize()
-    log(f"d0 leg: generated {n} events in {time.time() - t0:.1f}s")
-    b.autotune(tpasym.TP_PREC_F32_RECHECK)
+    log(f"{workload}: generated {n} events in {time.time() - t0:.1f}s")
+    b.autotune(prec)
     for _ in range(warmup):
-        b.run(tpasym.TP_PREC_F32_RECHECK, None, True)
+        b.run(prec, None, True)
     torch.cuda.synchronize()
     tpasym.timing_enable(True)
     tpasym.timing_reset()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):
-        b.run(tpasym.TP_PREC_F32_RECHECK, None, True)
+        b.run(prec, None, True)
     e1.record()
     torch.cuda.synchronize()
     kern_ms, _ = tpasym.timing_read()
@@ -418,10 +422,12 @@ def d0_leg(dev, steps, warmup):
                     "p": float(pv)})
     asym = tpasym.asym(c32.astype(np.int64))[0]
     achieved = n * BYTES_F32 / (kern_ms / 1e3) / 1e9
-    log(f"d0 leg: {ms:.3f} ms/step, {n / (ms / 1e3):.3e} events/s, {achieved:.0f} GB/s, "
+    log(f"{workload}: {ms:.3f} ms/step, {n / (ms / 1e3):.3e} events/s, {achieved:.0f} GB/s, "
         f"tier2 {int(st[4]) / reps / n:.2e}")
-    out = {"workload": "d0_kkpipi_5e8_m32x32", "events": n, "ms_per_step": ms, "value": n / (ms / 1e3),
-           "unit": "events/s", "dtype": "f32 sign tier, f64 recheck and bins",
+    phi = any(a.kind == synth.AXIS_ABSPHI for a in spec.axes)
+    out = {"workload": workload, "events": n, "ms_per_step": ms, "value": n / (ms / 1e3),
+           "unit": "events/s",
+           "dtype": "f64 first pass and bins on f32 storage" if phi else "f32 sign tier, f64 recheck and bins",
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS, "bytes_per_event": BYTES_F32, "kernel_ms": kern_ms},
            "tiers": {"tier2_frac": int(st[4]) / reps / n, "tier3_per_step": int(st[5]) / reps,
@@ -430,6 +436,30 @@ def d0_leg(dev, steps, warmup):
            "global": {"A_T": asym["A_T"][0], "Abar_T": asym["Abar_T"][0], "a_CP": asym["a_CP"][0],
                       "a_P": asym["a_P"][0]},
            "fp32": fp32_report([(ds, ch)], max_events=50_000_000)}
+    if chunk > 0:
+        # consecutive chunks of ``chunk`` events, one tp_bin call each
+        parts = [tpasym.DeviceSample([c[k:k + chunk] for c in ds.comps], ds.tag[k:k + chunk])
+                 for k in range(0, n, chunk)]
+        cc, cs = tpasym.new_counts(bn, dev)
+        for part in parts:
+            tpasym.bin(part, ch, bn, prec, counts=cc, stats=cs, check=False)
+        torch.cuda.synchronize()
+        cc.zero_()
+        cs.zero_()
+        e0.record()
+        for _ in range(steps):
+            for part in parts:
+                tpasym.bin(part, ch, bn, prec, counts=cc, stats=cs, check=False)
+        e1.record()
+        torch.cuda.synchronize()
+        cms = e0.elapsed_time(e1) / steps
+        cch = cc.cpu().numpy().view(np.uint64)
+        out["chunked"] = {"chunk_events": chunk, "chunks": len(parts), "ms_per_step": cms,
+                          "value": n / (cms / 1e3), "unit": "events/s",
+                          "counts_equal_whole_pass": bool(np.all(cch % steps == 0)
+                                                          and np.array_equal(cch // steps, c32))}
+        log(f"{workload}: {len(parts)} chunks of {chunk} events: {cms:.3f} ms/step")
+        del parts, cc, cs
     del ds, counts, stats, b, c64, s64
     torch.cuda.empty_cache()
     return out
@@ -462,6 +492,8 @@ def main():
                     help="events of the bounded oracle timing beside the energy-test leg")
     ap.add_argument("--energy-bkg-perms", type=int, default=164,
                     help="permutations of the background-subtracted (eq. 3) leg, 41 per launch (0 skips it)")
+    ap.add_argument("--no-pkpipi", action="store_true",
+                    help="skip the 1e8-event Lambda_b -> p K- pi+ pi- leg (10 phi x 8 m(p pi-) bins, also in 16M-event chunks)")
     ap.add_argument("--no-d0", action="store_true",
                     help="skip the 5e8-event D0 -> K+ K- pi+ pi- leg (32 x 32 mass bins)")
     ap.add_argument("--no-fp32-report", action="store_true",
@@ -659,8 +691,10 @@ def main():
             ok = ok and got == wantc
         out["parity_vs_oracle"] = {"samples_checked": len(orc), "counts_bit_exact": bool(ok)}
         log(f"cpu baseline {cpu['value']:.3e} events/s on {cpu['cores']} threads ({cpu['seconds']:.1f}s)")
+    if not args.no_pkpipi:
+        out["pkpipi_leg"] = single_leg(dev, "lb_pkpipi_1e8_phi10xm8", max(3, args.steps // 2), 2, chunk=1 << 24)
     if not args.no_d0:
-        out["d0_leg"] = d0_leg(dev, max(3, args.steps // 2), 2)
+        out["d0_leg"] = single_leg(dev, "d0_kkpipi_5e8_m32x32", max(3, args.steps // 2), 2)
     if args.energy_events > 0:
         out["energy_test"] = energy_leg(int(args.energy_events), args.energy_perms, dev,
                                         cpu_events=0 if args.no_cpu else args.energy_cpu_events)

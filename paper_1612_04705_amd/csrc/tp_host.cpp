@@ -711,15 +711,20 @@ int launch_plan(Device &d, const Plan &p, const std::vector<tp_tuning> &gtu, int
     kp.xdone = ws.xdone;
     kp.xcap = (uint32_t)ws.cap;
     kp.mode = mode;
-    // Several scheme groups run as parallel branches (group k on stream
-    // k mod (NSIDE + 1), stream 0 being the caller's): their launches overlap,
+    // Several scheme groups run as parallel branches (the caller's stream and
+    // NSIDE side streams, in turn): their launches overlap,
     // so one kernel's last workgroups share the chip with the next kernel's
     // first, and memory-bound and issue-bound schemes share the compute units.
     // The exact tier waits for all of them.  (Under graph capture the side
     // streams join the capture through the fork event and leave it through
     // the joins.)
     int ngroups = 0;
-    for (const Group &g : p.groups) ngroups += g.vend > g.vbeg;
+    size_t largest = 0;
+    for (size_t gi = 0; gi < p.groups.size(); ++gi) {
+        const Group &g = p.groups[gi];
+        ngroups += g.vend > g.vbeg;
+        if (g.vend - g.vbeg > p.groups[largest].vend - p.groups[largest].vbeg) largest = gi;
+    }
     const bool fork = only < 0 && ngroups > 1;
     bool joined[NSIDE] = {};
     if (fork) {
@@ -727,13 +732,15 @@ int launch_plan(Device &d, const Plan &p, const std::vector<tp_tuning> &gtu, int
         if (rc) return rc;
         TP_HIP(hipEventRecord(d.fork, st));
     }
-    int k = 0;
+    // the largest group (usually the last to finish) on the caller's stream,
+    // so that the exact tier follows it without a wait on another stream
+    int k = 1;
     for (size_t gi = 0; gi < p.groups.size(); ++gi) {
         if (only >= 0 && (size_t)only != gi) continue;
         const Group &g = p.groups[gi];
         const int64_t nv = g.vend - g.vbeg;
         if (nv <= 0) continue;
-        const int lane = fork ? k++ % (NSIDE + 1) : 0;
+        const int lane = !fork || gi == largest ? 0 : k++ % (NSIDE + 1);
         hipStream_t gs = st;
         if (lane > 0) {
             gs = d.side[lane - 1];
@@ -1273,58 +1280,18 @@ int tp_autotune(const tp_sample *samples, int32_t nsamples, int32_t precision, v
             overall = bt;
         }
     }
-    // the per-group combination against every single shape on the whole plan
-    // (groups interact through the tails between their launches)
-    auto measure_all = [&](const std::vector<tp_tuning> &gtu, int trials, float &ms) -> int {
-        int r = launch_plan(d, *p, gtu, precision, 0, ws, st);
-        ms = 1e30f;
-        for (int trial = 0; trial < trials && !r; ++trial) {
-            TP_HIP(hipEventRecord(a, st));
-            for (int k = 0; k < 3 && !r; ++k) r = launch_plan(d, *p, gtu, precision, 0, ws, st);
-            TP_HIP(hipEventRecord(b, st));
-            TP_HIP(hipEventSynchronize(b));
-            float m = 0;
-            TP_HIP(hipEventElapsedTime(&m, a, b));
-            ms = std::min(ms, m / 3);
-        }
-        return r;
-    };
-    if (!rc && p && p->groups.size() > 1) {
-        std::vector<tp_tuning> per(p->groups.size());
-        for (size_t g = 0; g < per.size(); ++g) per[g] = d.tuned[group_key(*p, p->groups[g], precision)];
-        float per_ms = 0;
-        rc = measure_all(per, 3, per_ms);
-        float uni_ms = 1e30f;
-        tp_tuning uni = cand[0];
-        for (size_t c = 0; c < cand.size() && !rc; ++c) {
-            float ms = 0;
-            rc = measure_all(std::vector<tp_tuning>(p->groups.size(), cand[c]), 2, ms);
-            if (ms < uni_ms) {
-                uni_ms = ms;
-                uni = cand[c];
-            }
-        }
-        if (!rc) {
-            float again = 0;
-            rc = measure_all(std::vector<tp_tuning>(p->groups.size(), uni), 3, again);
-            uni_ms = std::min(uni_ms, again);
-        }
-        if (!rc && uni_ms < per_ms) {
-            for (size_t g = 0; g < per.size(); ++g) d.tuned[group_key(*p, p->groups[g], precision)] = uni;
-            overall = uni;
-        }
-        static const bool verbose = std::getenv("TP_TUNE_VERBOSE") != nullptr;
-        if (verbose)
-            std::fprintf(stderr, "tp_tune: whole plan per-group %.4f ms, best single shape %.4f ms (epl %d wg/cu %d "
-                         "copies %d)\n", per_ms, uni_ms, uni.unroll, uni.wg_per_cu, uni.lds_copies);
-    }
+    // No whole-plan stage: the groups' launches overlap (parallel branches),
+    // and timing the whole plan as eager launches ranked some shapes wrongly
+    // for the graphed batch (two workgroups per CU for the largest group
+    // looked faster eagerly and ran 10-15 % slower as a graph); each group's
+    // own ranking held.
     g_timing.on = was_on;
     hipEventDestroy(a);
     hipEventDestroy(b);
     if (p && !rc) rc = end_use(*p, st);
     if (rc) return rc;
     // the whole request's entry (for callers that pass it explicitly): the
-    // largest group's shape, or the single shape that won
+    // largest group's shape
     *best = overall;
     d.tuned[tune_key(rq, precision)] = overall;
     save_tune_file(d);
