@@ -98,6 +98,51 @@ def test_batch_workload_shape(tp):
                 assert st[6] == 0
 
 
+def test_batch_with_six_scheme_groups(tp):
+    """A batch of six binning schemes (|Phi|, |Phi| x mass, |cos theta| x |Phi|, mass,
+    |cos theta| and none): six scheme groups, launched on parallel branches (more groups
+    than side streams, so branches are shared), eager and as a graph replayed three
+    times with eager work between the replays, every run against the oracle."""
+    ch = synth.CHANNELS["Lb_pKpipi"]
+    schemes = [[synth.absphi_axis(10)], [synth.absphi_axis(10), synth.lb_mass03_axis(ch)],
+               [synth.abscos_axis(0, 5), synth.absphi_axis(10)], [synth.lb_mass03_axis(ch, 6)],
+               [synth.abscos_axis(0, 4)], []]
+    items, wants = [], []
+    for k in range(12):
+        axes = schemes[k % 6]
+        s = synth.generate(ch, 3000 + 1777 * k, 900 + k, inj=synth.INJ_SIN2)
+        comps, tag = s.numpy()
+        wants.append(oracle.run(comps, tag, ch.triple, ch.planes, axes))
+        bn = tp.Binning(axes)
+        items.append((tp.DeviceSample.from_sample(s), tp.channel(ch.triple, ch.planes), bn, *tp.new_counts(bn)))
+    b = tp.Batch(items)
+
+    def verify(reps, label):
+        torch.cuda.synchronize()
+        for (ds, _, bn, counts, stats), w in zip(items, wants):
+            c = [int(x) for x in u64(counts)]
+            c = [c[4 * r:4 * r + 4] for r in range(bn.nrows)]
+            st = [int(x) for x in u64(stats)]
+            assert c == [[reps * v for v in row] for row in w["counts"]], label
+            assert st[:4] == [reps * v for v in w["stats"]], label
+            assert st[6] == 0, label
+
+    for prec in (tp.TP_PREC_F32_RECHECK, tp.TP_PREC_F64):
+        for it in items:
+            it[3].zero_()
+            it[4].zero_()
+        b.run(prec, None, False)
+        n = 1
+        verify(n, ("eager", prec))
+        for k in range(3):
+            b.run(prec, None, True)
+            n += 1
+            verify(n, ("graph replay", k, prec))
+            b.run(prec, None, False)          # eager work between the replays
+            n += 1
+            verify(n, ("eager after replay", k, prec))
+
+
 def test_compute_per_event_classes(tp):
     ch = synth.CHANNELS["Lb_ppipipi"]
     s = synth.generate(ch, 30011, 41)
