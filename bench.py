@@ -667,8 +667,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl, "samples": len(samples), "events": nevents,
                    "storage": "f64" if f64_store else "f32",
-                   "path": ("persistent batched pass, HIP graph" if graph else "persistent batched pass"),
-                   "precision": args.precision,
+                   "path": ("persistent batched pass, one kernel per binning scheme on parallel branches, HIP graph"
+                            if graph else "persistent batched pass, one kernel per binning scheme on parallel streams"),
+                   "requested_precision": ("TP_PREC_F32_RECHECK" if args.precision == "f32" else "TP_PREC_F64"),
                    "arithmetic": "float64 certified tiers on float32 storage (plane-angle schemes: the float32 "
                                  "sign tier does not run), double-word and exact integers for deferred events",
                    "tuning": tuning_desc},

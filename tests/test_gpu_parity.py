@@ -143,6 +143,52 @@ def test_batch_with_six_scheme_groups(tp):
             verify(n, ("eager after replay", k, prec))
 
 
+def test_release_and_reuse(tp):
+    """tp_release frees every device resource the library holds (plans, graphs,
+    workspaces, side streams and their events, the pair-sum flags); the next calls
+    recreate them.  A three-scheme batch (parallel branches), eager and graphed, and a
+    pair-sum launch before and after a release, each against the oracle."""
+    from oracle import energy
+    ch = synth.CHANNELS["Lb_ppipipi"]
+    schemes = [[synth.absphi_axis(10)], [synth.absphi_axis(10), synth.lb_mass03_axis(ch)],
+               [synth.abscos_axis(0, 5), synth.absphi_axis(10)]]
+    samples = [synth.generate(ch, 4000 + 999 * k, 950 + k, inj=synth.INJ_SIN) for k in range(3)]
+    wants = []
+    for s_, axes in zip(samples, schemes):
+        comps, tag = s_.numpy()
+        wants.append(oracle.run(comps, tag, ch.triple, ch.planes, axes))
+    rng = np.random.default_rng(951)
+    Y = rng.normal(1.0, 0.3, size=(3, 700)).astype(np.float32)
+    G = (rng.uniform(size=(700, 32)) < 0.5).astype(np.uint8)
+    Psi = energy.psi_block(Y.astype(np.float64), Y.astype(np.float64), 0.3)
+    np.fill_diagonal(Psi, 0.0)
+    want_sums = np.einsum("ic,ic->c", G.astype(np.float64), Psi @ G.astype(np.float64))
+
+    def once(label):
+        items = []
+        for s_, axes in zip(samples, schemes):
+            bn = tp.Binning(axes)
+            items.append((tp.DeviceSample.from_sample(s_), tp.channel(ch.triple, ch.planes), bn, *tp.new_counts(bn)))
+        b = tp.Batch(items)
+        b.run(tp.TP_PREC_F32_RECHECK, None, False)
+        b.run(tp.TP_PREC_F32_RECHECK, None, True)
+        torch.cuda.synchronize()
+        for (ds, _, bn, counts, stats), w in zip(items, wants):
+            c = [int(x) for x in u64(counts)]
+            c = [c[4 * r:4 * r + 4] for r in range(bn.nrows)]
+            assert c == [[2 * v for v in row] for row in w["counts"]], label
+            assert [int(x) for x in u64(stats)][:4] == [2 * v for v in w["stats"]], label
+        sums = tp.pairsums(torch.from_numpy(Y).cuda(), torch.from_numpy(G).cuda(), 0.3, nrow=0)
+        torch.cuda.synchronize()
+        got = sums.cpu().numpy()[:, 0]
+        assert np.all(np.abs(got - want_sums) <= 1e-5 * want_sums + 1e-9), label
+
+    once("before release")
+    torch.cuda.synchronize()
+    tp.release()
+    once("after release")
+
+
 def test_compute_per_event_classes(tp):
     ch = synth.CHANNELS["Lb_ppipipi"]
     s = synth.generate(ch, 30011, 41)
