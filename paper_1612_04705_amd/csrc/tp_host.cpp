@@ -547,38 +547,55 @@ int build_plan(Device &d, const std::vector<Req> &rq, int mode, hipStream_t st, 
     for (size_t r = 0; r < order.size(); ++r) order[r] = r;
     auto scheme = [&](size_t r) { return (ks[r].kind[0] * 4 + ks[r].kind[1]) * 2 + (ks[r].olo >= 0 ? 1 : 0); };
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return scheme(a) < scheme(b); });
+    // the pass kernels index each array with 32-bit offsets from its base: a
+    // sample whose arrays reach 2^32 bytes becomes several descriptors of at
+    // most ``cap`` events each (same counters; their events add up)
+    const int64_t cap = p->dtype == TP_F32 ? (int64_t(1) << 30) : (int64_t(1) << 29);
+    const size_t esize = p->dtype == TP_F32 ? 4 : 8;
     int64_t v = 0;
-    for (size_t r : order) {
-        KSample k = ks[r];
-        // samples start on multiples of 256 virtual events: workgroup ranges
-        // and tiles are multiples of 256 too, so every wave reads whole
-        // 128-byte lines of each component array (arrays 256-byte aligned)
-        k.vstart = v;
-        v += (k.n + 255) & ~int64_t(255);
-        const int sidx = (int)p->hs.size();
-        p->hs.push_back(k);
-        const bool ord = k.olo >= 0;
-        if (p->groups.empty() || p->groups.back().k0 != k.kind[0] || p->groups.back().k1 != k.kind[1] ||
-            p->groups.back().ord != ord) {
-            Group g;
-            g.k0 = k.kind[0];
-            g.k1 = k.kind[1];
-            g.ord = ord;
-            g.sbeg = sidx;
-            g.vbeg = k.vstart;
-            p->groups.push_back(g);
+    for (size_t r : order)
+        for (int64_t e0 = 0; e0 == 0 || e0 < ks[r].n; e0 += cap) {
+            KSample k = ks[r];
+            if (e0 > 0 || k.n > cap) {
+                for (int c = 0; c < 16; ++c) k.p[c] = static_cast<const char *>(k.p[c]) + e0 * esize;
+                k.tag += e0;
+                if (k.cls_out) k.cls_out += e0;
+                if (k.ct_out) k.ct_out += e0;
+                k.n = std::min(cap, ks[r].n - e0);
+            }
+            // samples start on multiples of 256 virtual events: workgroup ranges
+            // and tiles are multiples of 256 too, so every wave reads whole
+            // 128-byte lines of each component array (arrays 256-byte aligned)
+            k.vstart = v;
+            v += (k.n + 255) & ~int64_t(255);
+            const int sidx = (int)p->hs.size();
+            p->hs.push_back(k);
+            const bool ord = k.olo >= 0;
+            if (p->groups.empty() || p->groups.back().k0 != k.kind[0] || p->groups.back().k1 != k.kind[1] ||
+                p->groups.back().ord != ord) {
+                Group g;
+                g.k0 = k.kind[0];
+                g.k1 = k.kind[1];
+                g.ord = ord;
+                g.sbeg = sidx;
+                g.vbeg = k.vstart;
+                p->groups.push_back(g);
+            }
+            Group &g = p->groups.back();
+            g.send = sidx + 1;
+            g.vend = v;
+            // LDS histogram copy: class-total row, bin rows, overflow row, statistics
+            const int stride = (k.nbtot + 2) * 4 + NSTAT;
+            g.hist_stride = std::max(g.hist_stride, stride);
+            int ed = 0;
+            for (int a = 0; a < k.naxes; ++a) ed += edge_doubles(k.kind[a], k.nbins[a]);
+            g.edge_doubles = std::max(g.edge_doubles, ed);
         }
-        Group &g = p->groups.back();
-        g.send = sidx + 1;
-        g.vend = v;
-        // LDS histogram copy: class-total row, bin rows, overflow row, statistics
-        const int stride = (k.nbtot + 2) * 4 + NSTAT;
-        g.hist_stride = std::max(g.hist_stride, stride);
-        int ed = 0;
-        for (int a = 0; a < k.naxes; ++a) ed += edge_doubles(k.kind[a], k.nbins[a]);
-        g.edge_doubles = std::max(g.edge_doubles, ed);
-    }
     p->vtotal = v;
+    if (p->hs.size() > (size_t(1) << 20)) {   // the deferral list holds 20 bits of descriptor index
+        delete p;
+        return fail(TP_ERANGE, "too many samples once split at 2^32 bytes per array");
+    }
     if (p->hedges.empty()) p->hedges.push_back(0.0);
     const size_t sb = p->hs.size() * sizeof(KSample);
     const size_t eb = p->hedges.size() * sizeof(double);

@@ -19,7 +19,8 @@ enum { ST_EVENTS = 0, ST_ZERO = 1, ST_INVALID = 2, ST_OOR = 3, ST_TIER2 = 4, ST_
 struct KSample {
     const void *p[16];        // [kslot * 4 + c]
     const int8_t *tag;
-    int64_t n;
+    int64_t n;                // n * element size < 2^32: the kernels index the arrays with
+                              // 32-bit offsets (the host splits larger samples)
     int64_t vstart;           // start in the virtual event space (multiple of 256)
     uint64_t *counts;         // [(nbtot + 1) * 4]
     uint64_t *stats;          // [NSTAT]

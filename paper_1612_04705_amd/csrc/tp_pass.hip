@@ -727,13 +727,13 @@ __device__ __forceinline__ void load_scalar(ctab S, int64_t ev0, uint32_t off, u
     // they are re-read (scalar cache) per tile and occupy SGPRs only while the
     // tile's loads issue.
     asm volatile("" : "+s"(S));
-    const int8_t *tag = S->tag + ev0;
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
-        const uint32_t o = off + e < last ? off + e : last;
+        // index from the array base: below 2^32 bytes (the host splits larger samples)
+        const uint32_t o = (uint32_t)ev0 + (off + e < last ? off + e : last);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) q[e][k >> 2][k & 3] = ldnt<Tin>(static_cast<const Tin *>(S->p[k]) + ev0, o);
-        tg[e] = (int)ldnt<int8_t>(tag, o);
+        for (int k = 0; k < 16; ++k) q[e][k >> 2][k & 3] = ldnt<Tin>(S->p[k], o);
+        tg[e] = (int)ldnt<int8_t>(S->tag, o);
     }
 }
 
@@ -745,12 +745,13 @@ __device__ __forceinline__ void load_vector(ctab S, int64_t ev0, uint32_t off, T
 {
     constexpr int BYTES = EPL * (int)sizeof(Tin);
     asm volatile("" : "+s"(S));
-    const int8_t *tag = S->tag + ev0;
+    const void *tag = S->tag;
+    off += (uint32_t)ev0;   // from the array base (ev0 is a multiple of 256)
     if constexpr (BYTES == 8) {
         typedef Tin v2 __attribute__((ext_vector_type(2)));
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            const v2 v = ldnt<v2>(static_cast<const Tin *>(S->p[k]) + ev0, off >> 1);
+            const v2 v = ldnt<v2>(S->p[k], off >> 1);
             q[0][k >> 2][k & 3] = v.x;
             q[1][k >> 2][k & 3] = v.y;
         }
@@ -760,7 +761,7 @@ __device__ __forceinline__ void load_vector(ctab S, int64_t ev0, uint32_t off, T
     } else if constexpr (EPL == 4 && sizeof(Tin) == 4) {
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            const f32x4 v = ldnt<f32x4>(static_cast<const Tin *>(S->p[k]) + ev0, off >> 2);
+            const f32x4 v = ldnt<f32x4>(S->p[k], off >> 2);
             q[0][k >> 2][k & 3] = v.x;
             q[1][k >> 2][k & 3] = v.y;
             q[2][k >> 2][k & 3] = v.z;
@@ -772,7 +773,7 @@ __device__ __forceinline__ void load_vector(ctab S, int64_t ev0, uint32_t off, T
     } else if constexpr (EPL == 2) {   // double: 16-byte loads
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            const f64x2 v = ldnt<f64x2>(static_cast<const Tin *>(S->p[k]) + ev0, off >> 1);
+            const f64x2 v = ldnt<f64x2>(S->p[k], off >> 1);
             q[0][k >> 2][k & 3] = v.x;
             q[1][k >> 2][k & 3] = v.y;
         }

@@ -91,3 +91,39 @@ def test_full_size(tp, workload):
     assert np.array_equal(cls.index_select(0, idx).cpu().numpy(), want["cls"])
     del ds, s, b
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("tuning", [None, (256, 8, 4, 4)])
+def test_sample_past_2_to_32_bytes_per_array(tp, tuning):
+    """A float32 sample of 1025 * 2^20 events, more than 2^30: its component arrays pass
+    2^32 bytes, so the host splits it into two descriptors (the kernels index each array
+    with 32-bit offsets from a descriptor's base).  The sample is one 2^20-event sample
+    tiled 1025 times, so every count is exactly 1025 times the oracle's count for the
+    tile; scalar loads (default shape) and 16-byte vector loads (4 events per lane)."""
+    ch = synth.CHANNELS["Lb_pKpipi"]
+    axes = [synth.absphi_axis(10), synth.lb_mass03_axis(ch)]
+    small = synth.generate(ch, 1 << 20, 77, inj=synth.INJ_SIN2)
+    comps, tag = small.numpy()
+    want = oracle.run(comps, tag, ch.triple, ch.planes, axes)
+    reps = 1025
+    print(f"[full] {reps} x 2^20 events ({reps << 20}), tuning {tuning}", flush=True)
+    big = [torch.from_numpy(np.ascontiguousarray(comps[a, b])).cuda().repeat(reps) for a in range(4) for b in range(4)]
+    big_tag = torch.from_numpy(np.ascontiguousarray(tag)).cuda().repeat(reps)
+    ds = tp.DeviceSample(big, big_tag)
+    assert ds.n == reps << 20 and ds.n > (1 << 30)
+    bn = tp.Binning(axes)
+    chan = tp.channel(ch.triple, ch.planes)
+    counts, stats = tp.new_counts(bn)
+    if tuning is None:
+        tp.bin(ds, chan, bn, tp.TP_PREC_F32_RECHECK, counts, stats)
+    else:
+        tp.Batch([(ds, chan, bn, counts, stats)]).run(tp.TP_PREC_F32_RECHECK, tp.Tuning(*tuning), False, check=True)
+    torch.cuda.synchronize()
+    c = u64(counts)
+    c = [c[4 * r:4 * r + 4] for r in range(bn.nrows)]
+    st = u64(stats)
+    del big, big_tag, ds
+    torch.cuda.empty_cache()
+    assert c == [[reps * v for v in row] for row in want["counts"]]
+    assert st[:4] == [reps * v for v in want["stats"]]
+    assert st[6] == 0
