@@ -263,33 +263,51 @@ typedef struct {
 #define TP_BATCH_GRAPH 1    /* capture the launch in a HIP graph on first use and replay it */
 
 /*
- * tp_batch -- every sample of ``samples`` in one persistent launch: the
- * workgroups share the total event range, split into equal contiguous parts;
- * a workgroup switches descriptor and flushes its LDS histogram when it
- * crosses from one sample into the next.
- *   tuning: NULL = the autotuned (or default) shape for this workload class.
- *   flags: TP_BATCH_GRAPH to capture/replay a graph keyed by the exact sample set.
+ * tp_batch -- every sample of ``samples`` in one call.  The samples are grouped
+ * by binning scheme; each group is one persistent launch whose workgroups share
+ * the group's event range in equal contiguous parts (a workgroup switches
+ * descriptor and flushes its LDS histogram when it crosses from one sample into
+ * the next).  Several groups run as parallel branches: the largest on
+ * ``stream``, the others on internal side streams of the device (default
+ * priority) that wait for ``stream`` at the call and that ``stream`` waits for
+ * before the exact tier over the deferred events, so all work of the call is
+ * ordered on ``stream`` as one launch would be.  Calls on different streams of
+ * one device share the side streams, which orders their scheme launches among
+ * themselves (results are unaffected).  Samples whose arrays reach 2^32 bytes
+ * are passed as several descriptors internally (at most 2^20 descriptors in
+ * all, else TP_ERANGE).
+ *   tuning: NULL = each group's autotuned (or default) shape; else this shape
+ *   for every group.
+ *   flags: TP_BATCH_GRAPH to capture/replay a graph keyed by the exact sample
+ *   set, the shapes and the precision (the side streams join the capture).
  */
 int tp_batch(const tp_sample *samples, int32_t nsamples, int32_t precision,
              const tp_tuning *tuning, int32_t flags, void *stream);
 
 /*
- * tp_autotune -- time the candidate launch shapes on this batch (into internal
- * scratch counters: the samples' counts and stats are NOT touched), store the
- * best in the in-process cache (and in the JSON file named by TP_TUNE_CACHE if
- * set) and return it in *best.  Synchronises ``stream``.
+ * tp_autotune -- per scheme group of this batch, time the candidate launch
+ * shapes on that group's launch alone (into internal scratch counters: the
+ * samples' counts and stats are NOT touched), store each group's best in the
+ * in-process cache (and in the JSON file named by TP_TUNE_CACHE if set; a later
+ * process reads that file back) and return the largest group's in *best.
+ * Synchronises ``stream``.
  */
 int tp_autotune(const tp_sample *samples, int32_t nsamples, int32_t precision,
                 void *stream, tp_tuning *best);
 
-/* Average duration (ms) of the main pass kernel over the last ``tp_timing_reset``
- * window, measured with HIP events recorded on the launch stream around each
- * launch when timing is enabled (tp_timing_enable(1)).  Returns launches counted. */
+/* Average duration (ms) of the pass of one call -- from before its first pass
+ * launch to after the last scheme group has joined the launch stream, the exact
+ * tier excluded -- over the last ``tp_timing_reset`` window, measured with HIP
+ * events recorded on the launch stream (for a graph: around the graph launch,
+ * the exact tier included) when timing is enabled (tp_timing_enable(1)).
+ * Returns the launches counted. */
 int tp_timing_enable(int32_t on);
 int tp_timing_reset(void);
 int tp_timing_read(double *avg_ms, int64_t *launches);
 
-/* Release per-device internal state (workspaces, plans, graphs). */
+/* Release per-device internal state (workspaces, plans, graphs, side streams
+ * and their events, pair-sum flags); later calls recreate what they need.  The
+ * allocation-free entry point's device array stays until the process ends. */
 int tp_release(void);
 
 const char *tp_strerror(int status);
