@@ -69,7 +69,10 @@ typedef enum {
  * n elements, p[slot][c] with c = 0..3 for (E, px, py, pz) in MeV (any unit
  * works: everything is homogeneous), plus int8 flavour tags (0 = M, 1 = Mbar).
  * Arrays 16-byte aligned and n a multiple of 4 (float32) / 2 (float64) take
- * the vector-load path; anything else works through scalar loads. */
+ * the vector-load path; anything else works through scalar loads.  A sample
+ * of n = 0 events may carry NULL pointers: every call treats it as no work
+ * (its counts and statistics are left as they are, and tp_batch and
+ * tp_autotune leave it out of the plan). */
 typedef struct {
     int64_t n;
     int32_t dtype;            /* tp_dtype */
@@ -156,7 +159,8 @@ enum { TP_CLS_I = 0, TP_CLS_II = 1, TP_CLS_III = 2, TP_CLS_IV = 3, TP_CLS_ZERO =
 
 /*
  * tp_compute -- per-event triple product and class (Sect. 5, eq. (4)).
- *   cls_out: device int8[n] (class codes above) or NULL.
+ *   cls_out: device int8[n] (class codes above); required when n > 0 (the
+ *            later tiers write the classes of the events they decide there).
  *   ct_out:  device double[n] or NULL: C_T^inv = det[P; p_A; p_B; p_C] = M * C_T
  *            (float64 estimate; its SIGN is exact, 0.0 exactly for class zero).
  *   stats:   device tp_stats, accumulated (required).
@@ -290,7 +294,8 @@ int tp_batch(const tp_sample *samples, int32_t nsamples, int32_t precision,
  * samples' counts and stats are NOT touched), store each group's best in the
  * in-process cache (and in the JSON file named by TP_TUNE_CACHE if set; a later
  * process reads that file back) and return the largest group's in *best.
- * Synchronises ``stream``.
+ * Synchronises ``stream``.  With no event in any sample nothing is timed and
+ * *best is the default shape.
  */
 int tp_autotune(const tp_sample *samples, int32_t nsamples, int32_t precision,
                 void *stream, tp_tuning *best);

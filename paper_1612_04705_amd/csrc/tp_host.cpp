@@ -1052,9 +1052,9 @@ int tp_compute(const tp_events *ev, const tp_channel *ch, int32_t precision, int
     rc = check_channel(ch);
     if (rc) return rc;
     if (!stats) return fail(TP_EINVAL, "stats is NULL");
+    if (ev->n == 0) return TP_OK;   // per-event outputs of no elements may be NULL too
     if (!cls_out && !ct_out) return fail(TP_EINVAL, "tp_compute needs cls_out or ct_out");
     if (!cls_out) return fail(TP_EINVAL, "cls_out is required (the exact tier writes through it)");
-    if (ev->n == 0) return TP_OK;
     std::vector<Req> rq{ Req{ ev, ch, nullptr, nullptr, stats, cls_out, ct_out } };
     return run(rq, precision, 1, nullptr, 0, static_cast<hipStream_t>(stream));
 }
@@ -1170,9 +1170,9 @@ int tp_batch(const tp_sample *samples, int32_t nsamples, int32_t precision, cons
         if (!s.counts || !s.stats) return fail(TP_EINVAL, "counts and stats are required");
         if (dtype >= 0 && s.ev.dtype != dtype) return fail(TP_EUNSUPPORTED, "all samples of a batch share one dtype");
         dtype = s.ev.dtype;
-        rq.push_back(Req{ &s.ev, &s.ch, &s.bn, s.counts, s.stats, nullptr, nullptr });
+        if (s.ev.n > 0) rq.push_back(Req{ &s.ev, &s.ch, &s.bn, s.counts, s.stats, nullptr, nullptr });
     }
-    if (rq.empty()) return TP_OK;
+    if (rq.empty()) return TP_OK;   // nothing to launch (and no empty graph to capture)
     return run(rq, precision, 0, tuning, flags, static_cast<hipStream_t>(stream));
 }
 
@@ -1183,6 +1183,7 @@ int tp_autotune(const tp_sample *samples, int32_t nsamples, int32_t precision, v
     hipStream_t st = static_cast<hipStream_t>(stream);
     // validate and size a scratch sink
     size_t words = 0;
+    bool any_events = false;
     for (int i = 0; i < nsamples; ++i) {
         int rc = check_events(&samples[i].ev, precision);
         if (rc) return rc;
@@ -1195,6 +1196,13 @@ int tp_autotune(const tp_sample *samples, int32_t nsamples, int32_t precision, v
         int tot = 1;
         for (int a = 0; a < samples[i].bn.naxes; ++a) tot *= samples[i].bn.axis[a].nbins;
         words += (size_t)(tot + 1) * 4 + NSTAT;
+        any_events |= samples[i].ev.n > 0;
+    }
+    if (!any_events) {   // nothing to time: the default shape
+        tp_tuning t{};
+        defaults(t);
+        *best = t;
+        return TP_OK;
     }
     int dev = 0;
     int rc = current_device(dev);
@@ -1223,7 +1231,8 @@ int tp_autotune(const tp_sample *samples, int32_t nsamples, int32_t precision, v
             off += NSTAT;
         }
     }
-    for (auto &s : sink) rq.push_back(Req{ &s.ev, &s.ch, &s.bn, s.counts, s.stats, nullptr, nullptr });
+    for (auto &s : sink)
+        if (s.ev.n > 0) rq.push_back(Req{ &s.ev, &s.ch, &s.bn, s.counts, s.stats, nullptr, nullptr });
     std::vector<tp_tuning> cand;
     for (int epl : { 1, 2, 4 })
         for (int wpc : { 2, 4, 8 })

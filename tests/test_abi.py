@@ -283,3 +283,62 @@ def test_noalloc_limits_checked_before_the_device(tp):
     assert rc(_events(tp, dtype=7), good) == -1
     assert lib.tp_bin_noalloc(ctypes.byref(_events(tp)), ctypes.byref(ch), ctypes.byref(good.b), 0, None, st,
                               None) == -1
+
+
+def test_empty_samples_are_no_work(tp):
+    """A sample of n = 0 events may carry NULL pointers and is no work for every
+    entry point: each returns TP_OK before any device call (here, with no GPU, a
+    device call would fail).  tp_batch leaves empty samples out of its plan, so a
+    batch of only empty samples launches nothing (graph flag or not), and
+    tp_autotune of such a batch returns the default shape."""
+    from paper_1612_04705_amd import synth
+    lib = tp.load()
+    ch = tp.channel((0, 1, 2), (0, 1, 2, 3))
+    bins = [_bn(tp, [synth.absphi_axis(10)]), _bn(tp, [synth.abscos_axis(0, 5), synth.absphi_axis(10)]), _bn(tp, [])]
+    cnt = ctypes.c_void_p(0x200000)
+    st = ctypes.c_void_p(0x300000)
+    def empty(dtype):
+        e = _events(tp, n=0, dtype=dtype)
+        for k in range(16):
+            e.p[k] = None
+        e.tag = None
+        return e
+
+    for dtype in (0, 1):
+        e = empty(dtype)
+        assert lib.tp_bin(ctypes.byref(e), ctypes.byref(ch), ctypes.byref(bins[0].b), 0, cnt, st, None) == 0
+        assert lib.tp_bin_noalloc(ctypes.byref(e), ctypes.byref(ch), ctypes.byref(bins[0].b), 0, cnt, st,
+                                  None) == 0
+        assert lib.tp_compute(ctypes.byref(e), ctypes.byref(ch), 0, cnt, None, st, None) == 0
+        m = (ctypes.c_int32 * 2)(0b0011, 0b1100)
+        assert lib.tp_coords(ctypes.byref(e), m, 2, 1.0, 0, cnt, 0, None) == 0
+        arr = (tp._Sample * 3)()
+        for i, bn in enumerate(bins):
+            arr[i].ev = e
+            arr[i].ch = ch
+            arr[i].bn = bn.b
+            arr[i].counts = 0x200000 + 4096 * i
+            arr[i].stats = 0x300000 + 4096 * i
+        for flags in (0, 1):
+            assert lib.tp_batch(arr, 3, 0, None, flags, None) == 0
+        t = tp.Tuning()
+        assert lib.tp_autotune(arr, 3, 0, None, ctypes.byref(t)) == 0
+        assert (t.block, t.wg_per_cu, t.lds_copies, t.unroll) == (256, 4, 4, 1)
+    e = empty(0)
+    assert lib.tp_probe_f32(ctypes.byref(e), ctypes.byref(ch), cnt, cnt, cnt, cnt, None) == 0
+    # validation still applies to an empty sample
+    assert lib.tp_bin(ctypes.byref(empty(7)), ctypes.byref(ch), ctypes.byref(bins[0].b), 0, cnt, st, None) == -1
+    assert lib.tp_bin(ctypes.byref(empty(0)), ctypes.byref(ch), ctypes.byref(bins[0].b), 0, None, st, None) == -1
+
+
+def test_compute_output_checks(tp):
+    """tp_compute: with events, cls_out is required (NULL cls_out or no output at all
+    is TP_EINVAL before any device call); with none, NULL outputs are accepted."""
+    lib = tp.load()
+    ch = tp.channel((0, 1, 2), (0, 1, 2, 3))
+    st = ctypes.c_void_p(0x300000)
+    ct = ctypes.c_void_p(0x400000)
+    assert lib.tp_compute(ctypes.byref(_events(tp)), ctypes.byref(ch), 0, None, ct, st, None) == -1
+    assert lib.tp_compute(ctypes.byref(_events(tp)), ctypes.byref(ch), 0, None, None, st, None) == -1
+    assert lib.tp_compute(ctypes.byref(_events(tp)), ctypes.byref(ch), 0, ct, None, None, None) == -1
+    assert lib.tp_compute(ctypes.byref(_events(tp, n=0)), ctypes.byref(ch), 0, None, None, st, None) == 0

@@ -189,6 +189,79 @@ def test_release_and_reuse(tp):
     once("after release")
 
 
+def test_empty_samples(tp):
+    """Samples of no events (empty device tensors: NULL data pointers) are no work:
+    tp_bin, tp_compute and a batch of only such samples leave counts and statistics as
+    they are, eager and as a graph; in a batch beside non-empty samples of three
+    schemes (one scheme holding only an empty sample) the others match the oracle,
+    eager and on graph replays, and autotuning that batch works."""
+    ch = synth.CHANNELS["Lb_ppipipi"]
+    dev = torch.device("cuda")
+
+    def empty(dtype=torch.float32):
+        return tp.DeviceSample([torch.empty(0, dtype=dtype, device=dev) for _ in range(16)],
+                               torch.empty(0, dtype=torch.int8, device=dev))
+
+    def sentinel(bn):
+        counts, stats = tp.new_counts(bn)
+        counts.fill_(7)
+        stats.fill_(3)
+        return counts, stats
+
+    def untouched(counts, stats, label):
+        assert bool((counts == 7).all()) and bool((stats == 3).all()), label
+
+    chan = tp.channel(ch.triple, ch.planes)
+    bn = tp.Binning([synth.absphi_axis(10)])
+    for dtype, prec in ((torch.float32, tp.TP_PREC_F32_RECHECK), (torch.float64, tp.TP_PREC_F64)):
+        e = empty(dtype)
+        counts, stats = sentinel(bn)
+        tp.bin(e, chan, bn, prec, counts, stats, check=False)   # the sentinel counts 3 unresolved
+        cls, ct, st = tp.compute(e, chan, prec)
+        torch.cuda.synchronize()
+        untouched(counts, stats, ("tp_bin", dtype))
+        assert cls.numel() == 0 and int(st.abs().sum()) == 0
+        items = [(empty(dtype), chan, b, *sentinel(b))
+                 for b in (bn, tp.Binning([synth.abscos_axis(0, 5), synth.absphi_axis(10)]), tp.Binning([]))]
+        b = tp.Batch(items)
+        for graph in (False, True, True):
+            b.run(prec, None, graph)
+        t = b.autotune(prec)
+        assert (t.block, t.wg_per_cu, t.lds_copies, t.unroll) == (256, 4, 4, 1)
+        torch.cuda.synchronize()
+        for it in items:
+            untouched(it[3], it[4], ("all-empty batch", dtype))
+
+    schemes = [[synth.absphi_axis(10)], [synth.abscos_axis(0, 5), synth.absphi_axis(10)],
+               [synth.lb_mass03_axis(ch)]]
+    items, wants = [], []
+    for k, axes in enumerate([schemes[0], schemes[1], schemes[0], schemes[2], schemes[1]]):
+        bnk = tp.Binning(axes)
+        if k in (2, 3):             # scheme 2 holds only this empty sample
+            items.append((empty(), chan, bnk, *sentinel(bnk)))
+            wants.append(None)
+            continue
+        s = synth.generate(ch, 2000 + 1311 * k, 970 + k, inj=synth.INJ_SIN)
+        comps, tag = s.numpy()
+        wants.append(oracle.run(comps, tag, ch.triple, ch.planes, axes))
+        items.append((tp.DeviceSample.from_sample(s), chan, bnk, *tp.new_counts(bnk)))
+    b = tp.Batch(items)
+    b.autotune(tp.TP_PREC_F32_RECHECK)
+    n = 0
+    for graph in (False, True, True, False):
+        b.run(tp.TP_PREC_F32_RECHECK, None, graph)
+        n += 1
+        torch.cuda.synchronize()
+        for (ds, _, bnk, counts, stats), w in zip(items, wants):
+            if w is None:
+                untouched(counts, stats, ("empty in a mixed batch", graph, n))
+                continue
+            c = [int(x) for x in u64(counts)]
+            c = [c[4 * r:4 * r + 4] for r in range(bnk.nrows)]
+            assert c == [[n * v for v in row] for row in w["counts"]], (graph, n)
+            assert [int(x) for x in u64(stats)][:4] == [n * v for v in w["stats"]], (graph, n)
+
+
 def test_compute_per_event_classes(tp):
     ch = synth.CHANNELS["Lb_ppipipi"]
     s = synth.generate(ch, 30011, 41)
