@@ -99,10 +99,18 @@ def cpu_baseline(samples, budget_events, want_counts_of):
         model = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
     except Exception:
         model = "unknown"
+    # one thread on the first events of the largest sample timed above
+    spec, s = samples[max(used, key=lambda i: samples[i][1].n)]
+    m = min(s.n, 500000)
+    comps = np.stack([s.comps[a][b][:m].cpu().numpy() for a in range(4) for b in range(4)]).reshape(4, 4, -1)
+    t0 = time.perf_counter()
+    oracle.run(comps, s.tag[:m].cpu().numpy(), spec.channel.triple, spec.channel.planes, spec.axes, nthreads=1)
+    one = time.perf_counter() - t0
     return {"value": done / secs, "unit": "events/s", "cores": nthreads, "kind": "oracle",
             "sample": f"{len(used)} whole samples of the same workload ({done} events; float64 pass + exact "
                       f"resolution of flagged events; {model})",
-            "seconds": secs}, out
+            "seconds": secs,
+            "single_thread": {"value": m / one, "unit": "events/s", "events": m, "seconds": one}}, out
 
 
 # MI355X: 256 compute units x 4 SIMDs x 16 lanes x 2.4 GHz, one float32 vector
@@ -705,7 +713,8 @@ def main():
             wantc = [v for row in r["counts"] for v in row]
             ok = ok and got == wantc
         out["parity_vs_oracle"] = {"samples_checked": len(orc), "counts_bit_exact": bool(ok)}
-        log(f"cpu baseline {cpu['value']:.3e} events/s on {cpu['cores']} threads ({cpu['seconds']:.1f}s)")
+        log(f"cpu baseline {cpu['value']:.3e} events/s on {cpu['cores']} threads ({cpu['seconds']:.1f}s); "
+            f"one thread {cpu['single_thread']['value']:.3e} events/s")
     if not args.no_pkpipi:
         out["pkpipi_leg"] = single_leg(dev, "lb_pkpipi_1e8_phi10xm8", max(3, args.steps // 2), 2, chunk=1 << 24)
     if not args.no_d0:
