@@ -3,7 +3,8 @@
 Workload (default): the batched workload -- 64 independent samples, sizes
 log-uniform in [1e3, 1e7] events, four Lambda_b channels x three binning
 schemes (|Phi|; |Phi| x m(0,3); |cos theta_p| x |Phi|), float32 SoA storage,
-all in one persistent launch captured in a HIP graph, tuned by the autotuner.
+one persistent launch per binning scheme on parallel branches of one HIP
+graph, each scheme's launch shape tuned by the autotuner.
 One step = one pass of the whole hot path over the whole batch (every event:
 contraction, certified sign, class, bins, histogram, flush; the exact tier's
 list pass).  Inputs are generated on the GPU before timing and stay in HBM.
@@ -80,6 +81,8 @@ def cpu_baseline(samples, budget_events, want_counts_of):
     oracle.build(force=False)
     nthreads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     done, secs, used = 0, 0.0, []
+    t_pass = t_exact = 0.0
+    flagged = 0
     out = {}
     for i, (spec, s) in enumerate(samples):
         if done > 0 and done + s.n > budget_events:
@@ -89,6 +92,9 @@ def cpu_baseline(samples, budget_events, want_counts_of):
         t0 = time.perf_counter()
         r = oracle.run(comps, tag, spec.channel.triple, spec.channel.planes, spec.axes, nthreads=nthreads)
         secs += time.perf_counter() - t0
+        t_pass += r["seconds"]
+        t_exact += r["seconds_exact"]
+        flagged += r["n_flagged"]
         done += s.n
         used.append(i)
         if i in want_counts_of:
@@ -107,9 +113,12 @@ def cpu_baseline(samples, budget_events, want_counts_of):
     oracle.run(comps, s.tag[:m].cpu().numpy(), spec.channel.triple, spec.channel.planes, spec.axes, nthreads=1)
     one = time.perf_counter() - t0
     return {"value": done / secs, "unit": "events/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"{len(used)} whole samples of the same workload ({done} events; float64 pass + exact "
-                      f"resolution of flagged events; {model})",
+            "sample": f"{len(used)} whole samples of the same workload ({done} events; float64 pass on "
+                      f"{nthreads} threads, then exact rational resolution of the {flagged} events it flags, "
+                      f"one at a time on one thread; {model})",
             "seconds": secs,
+            # where the time goes: the threaded float64 pass, the serial exact stage
+            "seconds_float64_pass": t_pass, "seconds_exact_serial": t_exact, "flagged": flagged,
             "single_thread": {"value": m / one, "unit": "events/s", "events": m, "seconds": one}}, out
 
 
@@ -551,7 +560,9 @@ def main():
         t0 = time.time()
         largest = batch.autotune(prec)
         # runs without an explicit shape take each scheme group's tuned shape
-        tuning_desc = {"per_scheme_autotuned": True, "largest_group": largest.as_dict()}
+        tuning_desc = {"per_scheme_autotuned": True, "largest_group": largest.as_dict(),
+                       "overlapping_groups": "the largest launched at 16 workgroups per CU, the others "
+                                             "at most 4, whatever their tuned shapes"}
         log(f"autotune: per scheme group, largest group {largest.as_dict()} in {time.time() - t0:.1f}s")
     graph = not args.no_graph
     for _ in range(args.warmup):
@@ -713,8 +724,9 @@ def main():
             wantc = [v for row in r["counts"] for v in row]
             ok = ok and got == wantc
         out["parity_vs_oracle"] = {"samples_checked": len(orc), "counts_bit_exact": bool(ok)}
-        log(f"cpu baseline {cpu['value']:.3e} events/s on {cpu['cores']} threads ({cpu['seconds']:.1f}s); "
-            f"one thread {cpu['single_thread']['value']:.3e} events/s")
+        log(f"cpu baseline {cpu['value']:.3e} events/s on {cpu['cores']} threads ({cpu['seconds']:.1f}s: "
+            f"float64 pass {cpu['seconds_float64_pass']:.1f}s, serial exact stage {cpu['seconds_exact_serial']:.1f}s "
+            f"for {cpu['flagged']} flagged events); one thread {cpu['single_thread']['value']:.3e} events/s")
     if not args.no_pkpipi:
         out["pkpipi_leg"] = single_leg(dev, "lb_pkpipi_1e8_phi10xm8", max(3, args.steps // 2), 2, chunk=1 << 24)
     if not args.no_d0:

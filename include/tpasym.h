@@ -281,7 +281,8 @@ typedef struct {
  * are passed as several descriptors internally (at most 2^20 descriptors in
  * all, else TP_ERANGE).
  *   tuning: NULL = each group's autotuned (or default) shape; else this shape
- *   for every group.
+ *   for every group.  While groups run beside each other, the largest takes 16
+ *   workgroups per CU and the others at most 4, whatever the shape.
  *   flags: TP_BATCH_GRAPH to capture/replay a graph keyed by the exact sample
  *   set, the shapes and the precision (the side streams join the capture).
  */

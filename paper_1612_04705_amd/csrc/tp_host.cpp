@@ -158,6 +158,14 @@ constexpr int NSIDE = 3;
 // (batched 64-sample workload: 1.284 against 1.299 ms per step uncapped, 1.286
 // with 2; same box, three rounds each).
 constexpr int SIDE_WG_PER_CU = 4;
+// Workgroups per CU of the largest scheme group when others run beside it.
+// Each pass kernel holds 4 waves per SIMD, so a CU runs 4 of the launches'
+// workgroups at a time; the largest group's workgroups that find a free CU only
+// when a side launch drains still have their whole range to process, and the
+// step ends with them.  Finer ranges shorten that tail (batched 64-sample
+// workload: 16 against the tuned 8, 1.268 against 1.295 ms per step on one box
+// and 1.295 against 1.307 on another, three rounds each; 24 or 32 no better).
+constexpr int LARGEST_WG_PER_CU = 16;
 
 std::mutex g_mu;
 std::map<int, Device> g_dev;
@@ -770,9 +778,11 @@ int launch_plan(Device &d, const Plan &p, const std::vector<tp_tuning> &gtu, int
         }
         // beside the largest group, a group takes at most SIDE_WG_PER_CU
         // workgroups per CU, leaving the largest (the critical path) more of
-        // the chip from the start
+        // the chip from the start; the largest runs in finer ranges
+        // (LARGEST_WG_PER_CU)
         tp_tuning tu = gtu[gi];
         if (fork && gi != largest && tu.wg_per_cu > SIDE_WG_PER_CU) tu.wg_per_cu = SIDE_WG_PER_CU;
+        if (fork && gi == largest) tu.wg_per_cu = LARGEST_WG_PER_CU;
         const int rc = launch_group(d.cus, g, tu, p.dtype, prec, mode, kp, gs);
         if (rc) return rc;
     }
