@@ -258,7 +258,7 @@ typedef struct {
 /* Launch shape of the persistent pass.  Zero fields take defaults. */
 typedef struct {
     int32_t block;          /* threads per workgroup: 256 or 512                    */
-    int32_t wg_per_cu;      /* persistent workgroups per compute unit: 1..16        */
+    int32_t wg_per_cu;      /* persistent workgroups per compute unit: 1..32        */
     int32_t lds_copies;     /* LDS histogram copies per workgroup: 1 .. waves/WG    */
     int32_t unroll;         /* events per lane per step: 1, 2 or 4 (float32 storage;
                                float64 storage uses at most 2)                       */

@@ -647,7 +647,7 @@ int build_plan(Device &d, const std::vector<Req> &rq, int mode, hipStream_t st, 
 void defaults(tp_tuning &t)
 {
     if (t.block != 256 && t.block != 512) t.block = 256;
-    if (t.wg_per_cu < 1 || t.wg_per_cu > 16) t.wg_per_cu = 4;
+    if (t.wg_per_cu < 1 || t.wg_per_cu > 32) t.wg_per_cu = 4;
     const int waves = t.block / 64;
     if (t.lds_copies < 1 || t.lds_copies > waves) t.lds_copies = waves;
     if (t.unroll != 1 && t.unroll != 2 && t.unroll != 4) t.unroll = 1;
@@ -1243,12 +1243,12 @@ int tp_autotune(const tp_sample *samples, int32_t nsamples, int32_t precision, v
     }
     for (auto &s : sink)
         if (s.ev.n > 0) rq.push_back(Req{ &s.ev, &s.ch, &s.bn, s.counts, s.stats, nullptr, nullptr });
-    // 16 workgroups per CU (finer ranges: 4 rounds of the 4 resident
-    // workgroups) won for the single-scheme 10^8- and 5e8-event samples
-    // (1.1 and 3 % faster than 8)
+    // 16 and 32 workgroups per CU (finer ranges: 4 or 8 rounds of the 4
+    // resident workgroups) won for the single-scheme 10^8- and 5e8-event
+    // samples (16: 1.1 and 3 % faster than 8; 32: another 1.2 % on the latter)
     std::vector<tp_tuning> cand;
     for (int epl : { 1, 2, 4 })
-        for (int wpc : { 2, 4, 8, 16 })
+        for (int wpc : { 2, 4, 8, 16, 32 })
             for (int copies : { 1, 4 }) {
                 tp_tuning t;
                 t.block = 256;

@@ -370,6 +370,24 @@ def test_tuning_invariance(tp):
                 assert got == ref, t.as_dict()
 
 
+def test_fine_ranges_match_the_oracle(tp):
+    """16 and 32 workgroups per CU (the finest launch shapes the autotuner tries) on a
+    sample large enough that every workgroup of the grid gets its own range of several
+    tiles: counts bit-exact against the oracle for each shape."""
+    spec = synth.workload_specs("d0_kkpipi_5e8_m32x32", 0.0084)[0]
+    s = synth.make_sample(spec)
+    comps, tag = s.numpy()
+    want = oracle.run(comps, tag, spec.channel.triple, spec.channel.planes, spec.axes)
+    assert s.n > 256 * 32 * 256     # more tiles than workgroups at 32 per CU
+    for wpc in (8, 16, 32):
+        for copies, epl in ((1, 1), (4, 2)):
+            t = tp.Tuning(256, wpc, copies, epl)
+            counts, stats = gpu_bin(tp, s, spec.channel, spec.axes, tp.TP_PREC_F32_RECHECK, tuning=t)
+            print(f"[parity] fine ranges {t.as_dict()} n={s.n}", flush=True)
+            assert counts == want["counts"], t.as_dict()
+            assert stats[:4] == want["stats"] and stats[6] == 0, t.as_dict()
+
+
 def test_chunked_equals_whole(tp):
     spec = synth.workload_specs("lb_pkpipi_1e8_phi10xm8", 0.0003)[0]
     s = synth.make_sample(spec)
