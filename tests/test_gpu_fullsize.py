@@ -127,3 +127,42 @@ def test_sample_past_2_to_32_bytes_per_array(tp, tuning):
     assert c == [[reps * v for v in row] for row in want["counts"]]
     assert st[:4] == [reps * v for v in want["stats"]]
     assert st[6] == 0
+
+
+def test_full_size_batch(tp):
+    """The batched workload at full size (64 samples, 1.118e8 events) in the benchmark's
+    launch configuration: per-scheme tuned shapes, the scheme groups on parallel branches
+    (the largest at 16 workgroups per CU, the others at most 4), HIP graph, three steps.
+    Counts and statistics of every sample equal three times the plain single-sample float64
+    path's; the 16 smallest samples, whole, against the oracle."""
+    dev = torch.device("cuda:0")
+    specs = synth.workload_specs("lb_batch64_1e3to1e7", 1.0)
+    items, samples = [], []
+    for spec in specs:
+        s = synth.make_sample(spec, device=dev)
+        ds = tp.DeviceSample([s.comps[a][b] for a in range(4) for b in range(4)], s.tag)
+        bn = tp.Binning(spec.axes)
+        items.append((ds, tp.channel(spec.channel.triple, spec.channel.planes), bn, *tp.new_counts(bn, dev)))
+        samples.append((spec, s))
+    torch.cuda.synchronize()
+    print(f"[full] batch: {len(items)} samples, {sum(s.n for _, s in samples)} events generated", flush=True)
+    b = tp.Batch(items)
+    b.autotune(tp.TP_PREC_F32_RECHECK)
+    for _ in range(3):
+        b.run(tp.TP_PREC_F32_RECHECK, None, True)
+    torch.cuda.synchronize()
+    got = [(u64(it[3]), u64(it[4])) for it in items]
+    for k, ((ds, ch, bn, _, _), (c3, s3)) in enumerate(zip(items, got)):
+        c64, s64 = tp.bin(ds, ch, bn, tp.TP_PREC_F64)
+        c64, s64 = u64(c64), u64(s64)
+        assert c3 == [3 * v for v in c64], k
+        assert s3[:4] == [3 * v for v in s64[:4]] and s3[6] == 0, k
+    print("[full] batch: counts equal to the float64 single-sample path", flush=True)
+    for k in sorted(range(len(samples)), key=lambda i: samples[i][1].n)[:16]:
+        spec, s = samples[k]
+        comps = np.stack([s.comps[a][b].cpu().numpy() for a in range(4) for b in range(4)]).reshape(4, 4, -1)
+        want = oracle.run(comps, s.tag.cpu().numpy(), spec.channel.triple, spec.channel.planes, spec.axes)
+        assert got[k][0] == [3 * v for row in want["counts"] for v in row], k
+        assert got[k][1][:4] == [3 * v for v in want["stats"]], k
+    del items, samples, b
+    torch.cuda.empty_cache()
