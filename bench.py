@@ -560,9 +560,10 @@ def main():
         t0 = time.time()
         largest = batch.autotune(prec)
         # runs without an explicit shape take each scheme group's tuned shape
-        tuning_desc = {"per_scheme_autotuned": True, "largest_group": largest.as_dict(),
-                       "overlapping_groups": "the largest launched at 16 workgroups per CU, the others "
-                                             "at most 4, whatever their tuned shapes"}
+        tuning_desc = {"per_scheme_autotuned": True, "largest_group": largest.as_dict()}
+        if len({tuple(a.kind for a in sp.axes) for sp in specs}) > 1:     # several scheme groups
+            tuning_desc["overlapping_groups"] = ("the largest launched at 16 workgroups per CU, the others "
+                                                 "at most 4, whatever their tuned shapes")
         log(f"autotune: per scheme group, largest group {largest.as_dict()} in {time.time() - t0:.1f}s")
     graph = not args.no_graph
     for _ in range(args.warmup):
