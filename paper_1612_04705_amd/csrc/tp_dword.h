@@ -156,45 +156,6 @@ TP_HD inline int cos_le(int sX, int sF, double c)
     return -1;
 }
 
-// The |cos theta| bin of kernel slot s alone, for events whose sign and other
-// axis are already certified: #{k in 1..nb-1 : |cos theta| >= e_k}, or -1 when
-// a comparison is not certified (or the components lie outside the range the
-// bounds admit).  The quantities, their association order and the comparisons
-// are those of the |cos theta| axis in decide_dw, so where both decide they
-// agree bit for bit; this form skips the sign, the other Minkowski products and
-// every other axis.
-TP_HD inline int abscos_bin_dw(const double x[4][4], int s, const double *e, int nb)
-{
-    for (int t = 0; t < 4; ++t)
-        for (int c = 0; c < 4; ++c) {
-            const double a = aabs(x[t][c]);
-            if (!(a == 0.0 || (a >= 0x1p-30 && a <= 0x1p40))) return -1;
-        }
-    V P[4];
-    for (int c = 0; c < 4; ++c) {
-        V t = add(exact(x[0][c]), exact(x[1][c]));
-        t = add(t, exact(x[2][c]));
-        P[c] = add(t, exact(x[3][c]));
-    }
-    V M2 = mul(P[0], P[0]);
-    for (int c = 1; c < 4; ++c) M2 = sub(M2, mul(P[c], P[c]));
-    V d[4];
-    for (int b = 0; b < 4; ++b) d[b] = mink(x[s], x[b]);
-    const V PPs = add(add(d[0], d[1]), add(d[2], d[3]));
-    const V Nn = sub(mul(PPs, P[0]), mul(M2, exact(x[s][0])));
-    const V A = sub(mul(PPs, PPs), mul(M2, d[s]));
-    const V B = sub(mul(P[0], P[0]), M2);
-    const V AB = mul(A, B);
-    const V Nn2 = mul(Nn, Nn);
-    int j = 0;
-    for (int k = 1; k < nb; ++k) {
-        const int sF = csign(sub(Nn2, mul(prod(e[k], e[k]), AB)));
-        if (sF == 0) return -1;
-        j += sF > 0 ? 1 : 0;
-    }
-    return j;
-}
-
 // Decide one event (components x in kernel slot order, float values exactly in
 // double).  Same conventions as tpx::decide; returns W_UNCERTAIN when some
 // decision is not certified here.

@@ -33,13 +33,3 @@ extern "C" int hx_decide_dw(const double *comps, int tag, int sigma, int naxes, 
     const double *eds[2] = { e0, e1 };
     return tpw::decide_dw(x, tag, sigma, naxes, kind, nbins, slots, eds, *bin);
 }
-
-// The double-word |cos theta| bin of kernel slot s alone (the exact tier's form
-// for events whose sign and other axis are certified); -1 when undecided.
-extern "C" int hx_abscos_dw(const double *comps, int s, const double *e, int nb)
-{
-    double x[4][4];
-    for (int t = 0; t < 4; ++t)
-        for (int c = 0; c < 4; ++c) x[t][c] = comps[t * 4 + c];
-    return tpw::abscos_bin_dw(x, s, e, nb);
-}

@@ -109,36 +109,6 @@ def test_exact_tier_random_events(hx, chname, axes_fn, dtype):
     assert left == 0        # random events never need the integer tier
 
 
-@pytest.mark.parametrize("chname", ["Lb_ppiKK", "Lb_pKKK", "Lb_ppipipi", "Lb_pKpipi"])
-def test_double_word_abscos_axis_alone(hx, chname):
-    """The double-word |cos theta| bin alone (abscos_bin_dw: what the exact tier
-    recomputes once the sign and the plane angle are certified) against the
-    oracle's exact bin of that axis, on random events and at a boost of 1e4:
-    where it decides it agrees, and it decides nearly all of them."""
-    ch = synth.CHANNELS[chname]
-    axis = synth.abscos_axis(0, 5)
-    ax = [(axis.kind, axis.slots, list(map(float, axis.edges)))]
-    inv = [0] * 4
-    for t, s_ in enumerate(ch.planes):
-        inv[s_] = t
-    edges = (ctypes.c_double * len(ax[0][2]))(*ax[0][2])
-    total = decided = 0
-    for smp in (synth.generate(ch, 150, 41), synth.generate(ch, 60, 42, fixed_gamma=1e4)):
-        comps, tag = smp.numpy()
-        for i in range(comps.shape[2]):
-            ev = [[float(comps[a, c, i]) for c in range(4)] for a in range(4)]
-            cls, b = exact.exact_decision(ev, int(tag[i]), ch.triple, ch.planes, ax)
-            if cls >= 4:
-                continue
-            k = [ev[ch.planes[t]][c] for t in range(4) for c in range(4)]
-            j = hx.hx_abscos_dw((ctypes.c_double * 16)(*k), inv[axis.slots], edges, len(ax[0][2]) - 1)
-            total += 1
-            if j >= 0:
-                decided += 1
-                assert j == b, (chname, i, j, b)
-    assert decided >= 0.95 * total
-
-
 @pytest.mark.parametrize("gamma", [1e3, 1e5])
 def test_double_word_tier_extreme_boost(hx, gamma):
     ch = synth.CHANNELS["Lb_pKpipi"]
