@@ -262,6 +262,23 @@ def test_empty_samples(tp):
             assert [int(x) for x in u64(stats)][:4] == [n * v for v in w["stats"]], (graph, n)
 
 
+@pytest.mark.parametrize("chname,gamma", [("Lb_pKKK", 1e4), ("Lb_ppipipi", 3e3)])
+def test_abscos_absphi_at_high_boost(tp, chname, gamma):
+    """|cos theta| x |Phi| bins at boosts of 3e3 and 1e4, where the first pass defers most
+    events to the later tiers (double words, then exact integers): counts bit-exact against
+    the oracle, eager and as a graph, with thousands of events through those tiers."""
+    ch = synth.CHANNELS[chname]
+    axes = [synth.abscos_axis(0, 5), synth.absphi_axis(10)]
+    s = synth.generate(ch, 8000, 61, fixed_gamma=gamma)
+    comps, tag = s.numpy()
+    want = oracle.run(comps, tag, ch.triple, ch.planes, axes)
+    for graph in (False, True):
+        counts, stats = gpu_bin(tp, s, ch, axes, tp.TP_PREC_F32_RECHECK, graph=graph)
+        print(f"[parity] {chname} gamma={gamma} graph={graph} stats={stats}", flush=True)
+        assert stats[5] > 100 and stats[6] == 0
+        assert counts == want["counts"] and stats[:4] == want["stats"]
+
+
 def test_compute_per_event_classes(tp):
     ch = synth.CHANNELS["Lb_ppipipi"]
     s = synth.generate(ch, 30011, 41)
